@@ -1,0 +1,242 @@
+"""Seeded synthetic workloads: reaction networks, parameters and initial states.
+
+This module only *generates inputs*: stoichiometry tables, rate constants and
+initial copy numbers.  It holds none of the simulation method's arithmetic, so
+both the CPU oracle (tests) and the GPU path may use it.
+
+Networks are flat tables: ``m[j][i]`` is the number of molecules of species i
+consumed by reaction j (reactant order) and ``p[j][i]`` the number produced.
+The paper's own models (auto-regulatory gene network, Ras/cAMP/PKA, the stiff
+decaying-dimerizing set) ship as SBML files that are not available; the
+networks below are synthetic stand-ins with the shapes of the paper's
+examples (Results section).  The decaying-dimerizing set takes the constants
+c = (1, 0.002, 0.5, 0.04) from X0 = (10000, 0, 0); ``dimer_stiff`` speeds up
+its reversible pair so that implicit leaps occur.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_SIM = 160807058  # default Philox seed of the simulations
+
+
+@dataclass
+class Network:
+    name: str
+    m: np.ndarray          # [M][N] reactant orders
+    p: np.ndarray          # [M][N] product coefficients
+    theta: np.ndarray      # [M] nominal rate constants
+    x0: np.ndarray         # [N] nominal initial state
+    species: tuple = ()
+    reactions: tuple = ()
+
+    @property
+    def N(self) -> int:
+        return int(self.m.shape[1])
+
+    @property
+    def M(self) -> int:
+        return int(self.m.shape[0])
+
+
+def _net(name, m, p, theta, x0, species=(), reactions=()):
+    return Network(name, np.asarray(m, np.int32), np.asarray(p, np.int32),
+                   np.asarray(theta, np.float64), np.asarray(x0, np.int32),
+                   tuple(species), tuple(reactions))
+
+
+def birth_death(k1=10.0, k2=0.1, x0=0) -> Network:
+    """0 -> X (k1), X -> 0 (k2)."""
+    return _net("birth_death", [[0], [1]], [[1], [0]], [k1, k2], [x0], ("X",),
+                ("0->X", "X->0"))
+
+
+def dimer(x0=(10000, 0, 0)) -> Network:
+    """Decaying-dimerizing set: S1->0 (1), 2S1->S2 (0.002), S2->2S1 (0.5), S2->S3 (0.04)."""
+    m = [[1, 0, 0], [2, 0, 0], [0, 1, 0], [0, 1, 0]]
+    p = [[0, 0, 0], [0, 1, 0], [2, 0, 0], [0, 0, 1]]
+    return _net("dimer", m, p, [1.0, 0.002, 0.5, 0.04], x0, ("S1", "S2", "S3"),
+                ("S1->0", "2S1->S2", "S2->2S1", "S2->S3"))
+
+
+def dimer_stiff(scale=1000.0, x0=(10000, 0, 0)) -> Network:
+    """The decaying-dimerizing set with the reversible pair ``scale`` times faster.
+
+    With the constants of ``dimer()`` the pair never dominates the step-size
+    bound enough for an implicit leap; speeding it up makes the set stiff.
+    """
+    base = dimer(x0)
+    theta = base.theta.copy()
+    theta[1] *= scale
+    theta[2] *= scale
+    return _net("dimer_stiff", base.m, base.p, theta, x0, base.species, base.reactions)
+
+
+def isomerisation(kf=1.0, kb=1.0, n_total=1000) -> Network:
+    """A -> B (kf), B -> A (kb), all N_total molecules start as A."""
+    return _net("isomerisation", [[1, 0], [0, 1]], [[0, 1], [1, 0]], [kf, kb], [n_total, 0],
+                ("A", "B"), ("A->B", "B->A"))
+
+
+def schlogl(theta=(0.03, 1e-4, 200.0, 3.5), x0=250) -> Network:
+    """Schloegl model: 2X->3X, 3X->2X, 0->X, X->0 (bistable at these constants)."""
+    return _net("schlogl", [[2], [3], [0], [1]], [[3], [2], [1], [0]], theta, [x0], ("X",),
+                ("2X->3X", "3X->2X", "0->X", "X->0"))
+
+
+def telegraph() -> Network:
+    """Telegraph gene expression: species (G_off, G_on, mRNA, protein)."""
+    m = [[1, 0, 0, 0], [0, 1, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 1, 0], [0, 0, 0, 1]]
+    p = [[0, 1, 0, 0], [1, 0, 0, 0], [0, 1, 1, 0], [0, 0, 0, 0], [0, 0, 1, 1], [0, 0, 0, 0]]
+    return _net("telegraph", m, p, [0.05, 0.15, 20.0, 1.0, 2.0, 0.1], [1, 0, 0, 0],
+                ("G_off", "G_on", "mRNA", "protein"),
+                ("on", "off", "transcribe", "mRNA decay", "translate", "protein decay"))
+
+
+def random_network(seed=4, N=48, M=128, n_pairs=32, frac_uni=0.4, omega=1.0) -> Network:
+    """Seeded random mass-action network (large-network workload).
+
+    40 % unimolecular / 60 % bimolecular reactions (2A allowed), products of
+    1-2 species with coefficients 1-2.  Species get masses w in {1,2,3}; every
+    reaction satisfies w.p <= w.m so populations stay bounded, and ``n_pairs``
+    reversible pairs with w.p == w.m give partial equilibria.  Rate constants
+    are log-uniform on [1e-3, 1e2]; bimolecular constants are divided by the
+    system size ``omega``.  x0 is uniform on {50..500}.
+    """
+    rng = np.random.default_rng(seed)
+    w = rng.integers(1, 4, size=N)
+    m = np.zeros((M, N), np.int32)
+    p = np.zeros((M, N), np.int32)
+    j = 0
+
+    def draw_reactants(bi):
+        r = np.zeros(N, np.int32)
+        if not bi:
+            r[rng.integers(N)] = 1
+        else:
+            a, b = rng.integers(N), rng.integers(N)
+            r[a] += 1
+            r[b] += 1
+        return r
+
+    def draw_products(mass, exact):
+        # products of 1-2 species, coefficients 1-2, total mass <= mass (== if exact)
+        for _ in range(2000):
+            q = np.zeros(N, np.int32)
+            ns = rng.integers(1, 3)
+            for _s in range(ns):
+                q[rng.integers(N)] += rng.integers(1, 3)
+            pm = int(w @ q)
+            if (exact and pm == mass) or (not exact and pm <= mass):
+                return q
+        return None
+
+    n_uni = int(round(frac_uni * M))
+    kinds = np.array([0] * n_uni + [1] * (M - n_uni))
+    rng.shuffle(kinds)
+    # reversible pairs first (each uses two reaction slots)
+    pairs = []
+    while len(pairs) < n_pairs:
+        bi = bool(kinds[2 * len(pairs)])
+        r = draw_reactants(bi)
+        q = draw_products(int(w @ r), exact=True)
+        if q is None or np.array_equal(q, r):
+            continue
+        # the reverse reaction must have order <= 3 and consume exactly q
+        if q.sum() > 2:
+            continue
+        pairs.append((r, q))
+    for r, q in pairs:
+        m[j], p[j] = r, q
+        m[j + 1], p[j + 1] = q, r
+        j += 2
+    while j < M:
+        bi = bool(kinds[j])
+        r = draw_reactants(bi)
+        q = draw_products(int(w @ r), exact=False)
+        if q is None or np.array_equal(q, r):
+            continue
+        m[j], p[j] = r, q
+        j += 1
+    theta = 10.0 ** rng.uniform(-3.0, 2.0, size=M)
+    order = m.sum(axis=1)
+    theta = np.where(order >= 2, theta / omega, theta)
+    x0 = rng.integers(50, 501, size=N)
+    return _net(f"random{N}x{M}", m, p, theta, x0)
+
+
+# --------------------------------------------------------------------------
+# Ensembles: per-particle parameters and initial states.
+# --------------------------------------------------------------------------
+
+def tile(net: Network, P: int):
+    """Every particle gets the nominal theta and x0: theta [P][M], x0 [P][N]."""
+    theta = np.ascontiguousarray(np.broadcast_to(net.theta, (P, net.M)), dtype=np.float64)
+    x0 = np.ascontiguousarray(np.broadcast_to(net.x0, (P, net.N)), dtype=np.int32)
+    return theta, x0
+
+
+def gamma_prior_theta(net: Network, P: int, seed: int, shape: float = 2.0):
+    """theta_pj ~ Gamma(shape, rate = shape / theta_nom_j): mean theta_nom."""
+    rng = np.random.default_rng(seed)
+    scale = net.theta / shape
+    return rng.gamma(shape, scale, size=(P, net.M)).astype(np.float64)
+
+
+@dataclass
+class Workload:
+    name: str
+    nets: list
+    P: int
+    t_end: float
+    mode: str
+    eps: float = 0.03
+    theta: list = field(default_factory=list)   # per network: [P_k][M_k]
+    x0: list = field(default_factory=list)      # per network: [P_k][N_k]
+    pid: list = field(default_factory=list)     # per network: global particle ids [P_k]
+
+
+def birth_death_workload(P=1024) -> Workload:
+    net = birth_death()
+    th, x0 = tile(net, P)
+    return Workload("birth-death k1=10 k2=0.1 X0=0 t_end=100", [net], P, 100.0, "explicit",
+                    theta=[th], x0=[x0], pid=[np.arange(P, dtype=np.int64)])
+
+
+def dimer_workload(P=16384) -> Workload:
+    net = dimer()
+    th, x0 = tile(net, P)
+    return Workload("decaying-dimerizing X0=(10000,0,0) t_end=30", [net], P, 30.0, "adaptive",
+                    theta=[th], x0=[x0], pid=[np.arange(P, dtype=np.int64)])
+
+
+def mixed_set_workload(P=1 << 20, seed=3) -> Workload:
+    """Isomerisation / birth-death / Schloegl interleaved 1:1:1 (particle p uses
+    network p mod 3), theta from Gamma(2, 2/theta_nom) priors."""
+    nets = [isomerisation(), birth_death(), schlogl()]
+    th, x0, pid = [], [], []
+    for k, net in enumerate(nets):
+        ids = np.arange(k, P, 3, dtype=np.int64)
+        th.append(gamma_prior_theta(net, len(ids), seed + 100 * k))
+        x0.append(np.ascontiguousarray(np.broadcast_to(net.x0, (len(ids), net.N)), np.int32))
+        pid.append(ids)
+    return Workload("iso/birth-death/Schloegl 1:1:1, Gamma(2,2/theta) priors, t_end=50", nets,
+                    P, 50.0, "adaptive", theta=th, x0=x0, pid=pid)
+
+
+def random_network_workload(P=65536, seed=4, omega=100.0) -> Workload:
+    net = random_network(seed=seed, omega=omega)
+    th, x0 = tile(net, P)
+    return Workload(f"random mass-action N=48 M=128 (omega={omega:g}) t_end=10", [net], P, 10.0,
+                    "adaptive", theta=[th], x0=[x0], pid=[np.arange(P, dtype=np.int64)])
+
+
+def telegraph_workload(P=1 << 18, seed=5) -> Workload:
+    net = telegraph()
+    th = gamma_prior_theta(net, P, seed)
+    x0 = np.ascontiguousarray(np.broadcast_to(net.x0, (P, net.N)), np.int32)
+    return Workload("telegraph gene expression, 50 intervals of 5", [net], P, 5.0, "adaptive",
+                    theta=[th], x0=[x0], pid=[np.arange(P, dtype=np.int64)])
