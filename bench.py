@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark: trajectories/s and reaction-events/s on one MI355X.
+
+A step is one ``lx_simulate`` call over the whole ensemble of the
+decaying-dimerizing workload (16384 trajectories, X0 = (10000, 0, 0),
+t_end = 30, eps = 0.03, adaptive explicit/implicit/SSA): every step of the
+method runs inside it, inputs resident in HBM, outputs preallocated.  The
+headline form is the batched mixed-precision schedule; the plain fp64 form
+(one lane per trajectory for life) is timed beside it.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one
+GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "trajectories/s and reaction-events/s on 1 GPU, batched-mixed vs plain FP64"
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
+# (one fp64 or fp32 add/mul/fma, or one integer operation, per lane per cycle).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+FORMS = {
+    "plain_fp64": {"precision": "fp64", "schedule": "plain"},
+    "plain_mixed": {"precision": "mixed", "schedule": "plain"},
+    "batched_fp64": {"precision": "fp64", "schedule": "batched"},
+    "batched_mixed": {"precision": "mixed", "schedule": "batched"},
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--forms", default="batched_mixed,plain_fp64,plain_mixed,batched_fp64")
+    ap.add_argument("--headline", default="batched_mixed")
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def time_form(args, lx, h, theta, x0, wl, form, out):
+    import torch
+    opts = dict(FORMS[form])
+    if args.block_size:
+        opts["block_size"] = args.block_size
+    stream = torch.cuda.current_stream()
+
+    def launch():
+        lx.simulate(h, theta, x0, wl.t_end, wl.eps, wl.mode, out=out, stream=stream, **opts)
+
+    for _ in range(args.warmup):
+        launch()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        launch()
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms = sum(per) / len(per)
+    r_total = int(out["r"].sum(dtype=torch.int64).item())
+    stats = lx.stats_numpy(out["stats"])
+    return {
+        "ms_per_step": ms,
+        "wall_s": wall,
+        "trajectories_per_s": wl.P / (ms / 1e3),
+        "events_per_s": r_total / (ms / 1e3),
+        "events_per_trajectory": r_total / wl.P,
+        "attempts_per_trajectory": float(stats["attempts"].mean()),
+        "lane_status_ok": bool((stats["status"] == 0).all()),
+        "precision": opts["precision"],
+        "schedule": opts["schedule"],
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1608_07058_amd import lx, workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    wl = W.dimer_workload()
+    net = wl.nets[0]
+    theta = torch.as_tensor(wl.theta[0], device="cuda")
+    x0 = torch.as_tensor(wl.x0[0], device="cuda")
+    h = lx.Network(net.m, net.p)
+    forms = [f for f in args.forms.split(",") if f]
+    results = {}
+    for form in forms:
+        out = {
+            "x": torch.empty((wl.P, net.N), dtype=torch.int32, device="cuda"),
+            "r": torch.empty((wl.P, net.M), dtype=torch.int32, device="cuda"),
+            "G": torch.empty((wl.P, net.M), dtype=torch.float64, device="cuda"),
+            "stats": torch.empty((wl.P, lx.STATS_WORDS), dtype=torch.int64, device="cuda"),
+        }
+        try:
+            results[form] = time_form(args, lx, h, theta, x0, wl, form, out)
+        except lx.LxError as exc:
+            results[form] = {"error": str(exc)}
+        log(args, f"[bench] {form}: {results[form]}")
+    head = args.headline if "error" not in results.get(args.headline, {"error": 1}) else None
+    if head is None:
+        ok = [f for f in forms if "error" not in results[f]]
+        head = ok[0]
+    hr = results[head]
+
+    # Algorithmic work per trajectory, counted by the oracle on the same
+    # workload (its trajectories are the kernels' trajectories).
+    cpu = None
+    ops_per_traj = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
+        t0 = time.perf_counter()
+        ref = oracle.simulate(net.m, net.p, wl.theta[0], wl.x0[0], wl.t_end, mode=wl.mode,
+                              nthreads=nth)
+        dt = time.perf_counter() - t0
+        ops_per_traj = float(ref["stats"]["ops"].mean())
+        cpu = {"value": wl.P / dt, "unit": "trajectories/s", "cores": nth, "kind": "oracle",
+               "sample": f"all {wl.P} trajectories of the workload, fp64 oracle, {nth} threads, "
+                         f"{dt:.1f} s"}
+        log(args, f"[bench] oracle: {cpu}")
+    roof = None
+    if ops_per_traj is not None:
+        achieved = ops_per_traj * wl.P / (hr["ms_per_step"] / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                "ops_per_trajectory": ops_per_traj, "kernel": "lx_sim_" + hr["schedule"]}
+    dtype = "f32+f64" if hr["precision"] == "mixed" else "f64"
+    line = {
+        "metric": METRIC,
+        "value": hr["trajectories_per_s"],
+        "unit": "trajectories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hr["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "trajectories": wl.P, "t_end": wl.t_end, "eps": wl.eps,
+                   "mode": wl.mode, "form": head, "precision": hr["precision"],
+                   "schedule": hr["schedule"]},
+        "events_per_s": hr["events_per_s"],
+        "forms": results,
+        "speedup_vs_plain_fp64": (hr["trajectories_per_s"] /
+                                  results["plain_fp64"]["trajectories_per_s"]
+                                  if "trajectories_per_s" in results.get("plain_fp64", {}) else None),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

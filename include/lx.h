@@ -1,0 +1,221 @@
+/* lx.h -- C ABI of liblx: ensemble adaptive explicit/implicit tau-leaping on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library advances P independent trajectories of a mass-action reaction
+ * network to a final time, one trajectory per GPU lane, with the adaptive
+ * explicit/implicit tau-leaping method packaged by matLeap (Feigelman,
+ * Ganscha & Claassen, arXiv 1608.07058), and returns for every trajectory the
+ * final state X(t_end), the firing counts r_j and the integrals G_j of g_j(X)
+ * that feed the conjugate Gamma(alpha_j + r_j, beta_j + G_j) posterior
+ * (Background section of the paper).
+ *
+ * Conventions
+ *  - Every function returns an lx_status; LX_OK (0) on success, a negative
+ *    code on error.  lx_last_error() returns a thread-local message for the
+ *    last non-OK status.  No C++ exception crosses this interface.
+ *  - Buffers marked "device" are GPU memory owned by the caller (e.g. torch
+ *    tensors); the library never frees them.  Host arrays are read during the
+ *    call only.
+ *  - Work is enqueued on the caller's HIP stream (passed as void*, NULL for
+ *    the default stream) and is asynchronous: the call returns once the
+ *    kernels are launched.  Argument and launch errors are reported
+ *    synchronously.  Per-trajectory conditions are reported in lx_stats.
+ *  - Network handles are immutable after creation; simulations with distinct
+ *    handles may run from different host threads.  A handle may be shared by
+ *    threads; its kernel cache is internally locked.
+ *  - The first simulation of a network with given precision/schedule compiles
+ *    a network-specialised kernel (hipRTC, gfx950) and caches the code object
+ *    in memory and in the directory named by LX_KERNEL_CACHE (default: a
+ *    "kcache" directory beside liblx.so).
+ */
+#ifndef LX_H_
+#define LX_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lx_status;
+#define LX_OK 0
+#define LX_E_INVALID (-1)     /* invalid argument or network table */
+#define LX_E_COMPILE (-2)     /* run-time kernel compilation failed */
+#define LX_E_HIP (-3)         /* HIP runtime error (launch, module load) */
+#define LX_E_UNSUPPORTED (-4) /* device is not gfx950, or network too large */
+#define LX_E_NOMEM (-5)       /* host or device allocation failed */
+
+/* Simulation modes (paper, Results section: adaptive by default, or fully
+ * explicit tau-leaping, or SSA only). */
+#define LX_MODE_ADAPTIVE 0 /* explicit/implicit/SSA switching */
+#define LX_MODE_EXPLICIT 1 /* explicit leaps and SSA bursts, never implicit */
+#define LX_MODE_SSA 2      /* exact SSA (Gillespie direct method) only */
+
+/* Precision policies. */
+#define LX_PREC_FP64 0  /* every floating-point quantity in binary64 */
+#define LX_PREC_MIXED 1 /* propensities, tau bounds, Poisson means and samplers in
+                           binary32; time t, G and the implicit Newton solve in
+                           binary64; counts int32 */
+
+/* Schedules. */
+#define LX_SCHED_PLAIN 0   /* one lane per particle for its whole life */
+#define LX_SCHED_BATCHED 1 /* persistent blocks, work-stealing refill of finished
+                              lanes and regrouping of lanes by action */
+
+/* Per-trajectory status codes (lx_stats.status). */
+#define LX_LANE_OK 0
+#define LX_LANE_STEP_BUDGET 1     /* max_steps attempts used before t_end */
+#define LX_LANE_LAMBDA_OVERFLOW 2 /* a Poisson mean beyond the sampler's range
+                                     (2^30 in fp64, 2^22 in mixed) */
+#define LX_LANE_BAD_INPUT 3       /* negative/non-finite theta or negative x0 */
+#define LX_LANE_COUNT_OVERFLOW 4  /* a copy number or firing count beyond int32 */
+
+/* Options.  Obtain defaults from lx_options_default() and override fields.
+ * The control constants are the tuning parameters the paper leaves to its
+ * supplement (Implementation section); the defaults are stated readings. */
+typedef struct lx_options {
+  int32_t precision;    /* LX_PREC_*                          default FP64 */
+  int32_t schedule;     /* LX_SCHED_*                         default PLAIN */
+  uint64_t seed;        /* Philox key                         default 160807058 */
+  uint32_t rng_stream;  /* added to the high key word (e.g. an interval index) */
+  uint32_t pid_base;    /* particle p uses RNG particle id pid_base + p */
+  double t_start;       /* start time                         default 0 */
+  int32_t accumulate;   /* nonzero: r_out and G_out hold starting values and
+                           are accumulated into (split runs) */
+  int32_t n_c;          /* critical threshold on L_j          default 10 */
+  double delta;         /* partial-equilibrium tolerance      default 0.05 */
+  double n_stiff;       /* implicit if tau_im > n_stiff*tau_ex, default 100 */
+  double k_ssa;         /* SSA burst if tau' < k_ssa / a0     default 10 */
+  double k_crit;        /* SSA burst if a0c >= a0 / k_crit    default 10 */
+  int32_t n_ssa_ex;     /* SSA burst length after an explicit choice, default 100 */
+  int32_t n_ssa_im;     /* SSA burst length after an implicit choice, default 10 */
+  double lambda_thr;    /* Poisson inversion below, PTRS above, default 10, in [1,30] */
+  double newton_tol;    /* Newton stop: |dy|inf <= tol*max(1,|y|inf), default 1e-10 */
+  int32_t newton_maxit; /* default 20 */
+  int32_t block_size;   /* threads per block (64..256, multiple of 64); 0 = default 64 */
+  int64_t max_steps;    /* attempt budget per trajectory      default 10^7 (< 2^32) */
+  int32_t chunk;        /* batched: particles per cursor grab, 0 = default */
+  int32_t regroup;      /* batched: loop iterations between regroups, 0 = default */
+  int32_t blocks_per_cu;/* batched: resident blocks per CU, 0 = default */
+  int32_t reserved[7];
+} lx_options;
+
+/* Per-trajectory statistics (80 bytes). */
+typedef struct lx_stats {
+  int32_t status; /* LX_LANE_* */
+  int32_t pad;
+  double t_final; /* time reached (t_end unless status != OK) */
+  int64_t steps_ssa, steps_explicit, steps_implicit; /* accepted actions by kind */
+  int64_t rejections;   /* leap attempts rejected (negative state, failed solve) */
+  int64_t newton_iters; /* Newton iterations */
+  int64_t newton_fail;  /* implicit solves that did not converge */
+  int64_t kclip;        /* implicit counts clipped at zero */
+  int64_t attempts;     /* SSA steps + leap attempts (RNG attempt index) */
+} lx_stats;
+
+typedef struct lx_network_s* lx_network;
+
+/* Fill *opt with the defaults above.  opt must be non-null. */
+void lx_options_default(lx_options* opt);
+
+/* Thread-local message describing the last non-OK status of this thread. */
+const char* lx_last_error(void);
+
+/* Compile a network from a flat table (paper, Background section: mass-action
+ * propensities a_j = theta_j g_j(X), g_j a function of the reactant copy
+ * numbers).
+ *   N, M              species and reactions, N, M >= 1.
+ *   reactant_order    host int32 [M][N], m_ij >= 0 molecules of species i
+ *                     consumed by reaction j; order_j = sum_i m_ij <= 3.
+ *   product_coeff     host int32 [M][N], p_ij >= 0 molecules produced.
+ * g_j(X) = prod_i C(X_i, m_ij) (distinct-combination convention).
+ * Errors: LX_E_INVALID for a bad table or N*M too large (M <= 32 and
+ * N <= 16 for the register-resident kernels).  *out receives a handle owned
+ * by the caller and released with lx_network_destroy. */
+lx_status lx_network_create(int32_t N, int32_t M, const int32_t* reactant_order,
+                            const int32_t* product_coeff, lx_network* out);
+
+/* Compile (hipRTC, gfx950) and cache on disk the simulation kernel of a
+ * network for a precision, schedule and block size (0 = default) without
+ * running it; needs no GPU.  Optional: lx_simulate compiles on first use. */
+lx_status lx_network_prepare(lx_network net, int32_t precision, int32_t schedule,
+                             int32_t block_size);
+
+/* Release a handle and its compiled kernels.  NULL is accepted. */
+lx_status lx_network_destroy(lx_network net);
+
+/* Query sizes and the number of reversible pairs found (reactions with
+ * exactly opposite net-change vectors, paired in ascending index). */
+lx_status lx_network_info(lx_network net, int32_t* N, int32_t* M, int32_t* n_pairs);
+
+/* Simulate P trajectories from t_start to t_end (paper: Implementation
+ * section -- adaptive explicit-implicit tau-leaping with critical reactions,
+ * the implicit switch when excluding reaction pairs in partial equilibrium
+ * gives a much larger leap, and the switch to SSA when the wait for the next
+ * critical reaction is comparable to the wait for the next reaction; tau
+ * bounded by the relative change of the propensities with accuracy eps,
+ * Background section).
+ *   theta   device double [P][M]: rate constants per trajectory (>= 0, finite).
+ *   x0      device int32  [P][N]: initial copy numbers (>= 0).
+ *   t_end   final time (>= opt->t_start); eps > 0 (the paper uses 0.03).
+ *   mode    LX_MODE_*.
+ *   opt     options or NULL for the defaults.
+ *   x_out   device int32  [P][N]: X(t_end).
+ *   r_out   device int32  [P][M]: firing counts (input too if accumulate).
+ *   G_out   device double [P][M]: integral of g_j over [t_start, t_end] --
+ *           trapezoid rule over leaps, exact over SSA steps (input too if
+ *           accumulate).
+ *   stats   device lx_stats [P] or NULL.
+ *   stream  hipStream_t or NULL.
+ * Rows are trajectories, row-major.  Results depend only on (seed,
+ * rng_stream, pid_base + p) and the inputs, never on the schedule or block
+ * size.  P = 0 is a no-op.  Errors: LX_E_INVALID (null pointers with P > 0,
+ * bad options), LX_E_UNSUPPORTED (not gfx950), LX_E_COMPILE, LX_E_HIP. */
+lx_status lx_simulate(lx_network net, int64_t P, const double* theta, const int32_t* x0,
+                      double t_end, double eps, int32_t mode, const lx_options* opt,
+                      int32_t* x_out, int32_t* r_out, double* G_out, lx_stats* stats,
+                      void* stream);
+
+/* ---- Test hooks: run the production device functions on fixed inputs. ----
+ * All pointers are device memory; n elements; enqueued on stream. */
+
+/* Philox4x32-10 (Salmon et al. 2011): ctr [n][4], key [n][2] -> out [n][4]. */
+lx_status lx_test_philox(int64_t n, const uint32_t* ctr, const uint32_t* key, uint32_t* out,
+                         void* stream);
+/* Uniform maps: f64 from word pairs w [n][2]; f32 from words w [n]. */
+lx_status lx_test_uniform_f64(int64_t n, const uint32_t* w, double* out, void* stream);
+lx_status lx_test_uniform_f32(int64_t n, const uint32_t* w, float* out, void* stream);
+/* Elementary functions used by the samplers: fn = 0 exp_f64, 1 log_f64,
+ * 2 lfact (log k!), 3 sqrt_f64 (in/out double); 10 exp_f32, 11 log_f32,
+ * 12 sqrt_f32 (in/out float). */
+lx_status lx_test_math(int32_t fn, int64_t n, const void* in, void* out, void* stream);
+/* Poisson(lam[q]) drawn at site (pid[q], e[q], site[q]) with key (seed,
+ * stream_id); precision LX_PREC_*; out int64 (-1 = beyond range). */
+lx_status lx_test_poisson(int64_t n, const double* lam, const uint32_t* pid, const uint32_t* e,
+                          const uint32_t* site, uint64_t seed, uint32_t stream_id,
+                          double lambda_thr, int32_t precision, int64_t* out, void* stream);
+/* Exponential(1) = -log(U) at site (pid[q], e[q], SSA site). */
+lx_status lx_test_exponential(int64_t n, const uint32_t* pid, const uint32_t* e, uint64_t seed,
+                              uint32_t stream_id, int32_t precision, double* out, void* stream);
+/* Step decision for Q states of a network: propensities a [Q][M] (as double),
+ * critical and equilibrium masks crit/eq [Q] (bit j = reaction j), tau [Q][2]
+ * = (tau_ex, tau_im or +inf), action [Q] (0 explicit leap, 1 implicit leap,
+ * 2 SSA burst, 3 absorbing).  theta [Q][M], x [Q][N].  Uses opt->precision
+ * and the control constants; eps and mode as in lx_simulate. */
+lx_status lx_test_tau_select(lx_network net, int64_t Q, const double* theta, const int32_t* x,
+                             double eps, int32_t mode, const lx_options* opt, double* a,
+                             uint32_t* crit, uint32_t* eq, double* tau, int32_t* action,
+                             void* stream);
+/* Implicit-leap solve for Q cases: given tau [Q], Poisson draws Pj [Q][M]
+ * (int64) and critical firing jc [Q] (-1 none), the non-critical set
+ * {j : a_j > 0, j != jc}; outputs k [Q][M] (int64), ok [Q], iters [Q]. */
+lx_status lx_test_implicit(lx_network net, int64_t Q, const double* theta, const int32_t* x,
+                           const double* tau, const int64_t* Pj, const int32_t* jc,
+                           const lx_options* opt, int64_t* k, int32_t* ok, int32_t* iters,
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LX_H_ */

@@ -48,7 +48,7 @@ STATS_DTYPE = np.dtype([
     ("status", np.int32), ("pad", np.int32), ("t_final", np.float64),
     ("steps_ssa", np.int64), ("steps_explicit", np.int64), ("steps_implicit", np.int64),
     ("rejections", np.int64), ("newton_iters", np.int64), ("newton_fail", np.int64),
-    ("kclip", np.int64), ("attempts", np.int64),
+    ("kclip", np.int64), ("attempts", np.int64), ("ops", np.int64),
 ])
 
 
@@ -139,6 +139,7 @@ def simulate(m, p, theta, x0, t_end, *, r0=None, G0=None, **kw):
     P = theta.shape[0]
     if theta.shape != (P, M) or x0.shape != (P, N):
         raise ValueError("theta must be [P][M] and x0 [P][N]")
+    kw.setdefault("nthreads", min(16, os.cpu_count() or 1))
     o = options(**kw)
     x = np.empty((P, N), np.int32)
     r = np.zeros((P, M), np.int32) if r0 is None else np.array(r0, dtype=np.int32, copy=True)

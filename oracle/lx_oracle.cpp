@@ -53,6 +53,17 @@
 
 namespace {
 
+// Algorithmic operation count of the current trajectory (lane-level
+// arithmetic, comparison and integer operations the method performs; a
+// division or square root counts as one operation).  Used only to state the
+// work behind a measured time; it does not affect any result.
+thread_local uint64_t g_ops = 0;
+inline void count_ops(uint64_t n) { g_ops += n; }
+const uint64_t OPS_PHILOX = 100;  // 10 rounds x (2 mul-hi, 2 mul-lo, 4 xor, 2 key adds)
+const uint64_t OPS_EXP = 20;      // 4 reduction, 13 fma, scale, 2 range tests
+const uint64_t OPS_LOG = 30;      // split, 3 for f/s, 11 series, 8 assembly, tests
+const uint64_t OPS_UNIFORM = 4;
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Counter-based: the
 // output is a pure function of a 128-bit counter and a 64-bit key.
@@ -107,6 +118,7 @@ struct Rng {
   void block(uint32_t e, uint32_t site, uint32_t trial, uint32_t out[4]) const {
     uint32_t ctr[4] = {pid, e, site, trial};
     philox4x32_10(ctr, key, out);
+    count_ops(OPS_PHILOX);
   }
 };
 
@@ -227,6 +239,7 @@ float log_f32(float x) {
 // Stirling's series for log Gamma(n), n = k + 1, with four correction terms
 // beyond that.
 double lfact_f64(double k) {
+  count_ops(k <= 17.0 ? (uint64_t)k + OPS_LOG : 16 + OPS_LOG);
   if (k <= 17.0) {
     double prod = 1.0;
     for (double i = 2.0; i <= k; i = i + 1.0) prod = prod * i;
@@ -244,10 +257,11 @@ double lfact_f64(double k) {
 // means and sampler arithmetic; time, G and the implicit solve are double.
 struct PolicyF64 {
   typedef double R;
-  static R ulog(R x) { return log_f64(x); }
-  static R uexp(R x) { return exp_f64(x); }
+  static R ulog(R x) { count_ops(OPS_LOG); return log_f64(x); }
+  static R uexp(R x) { count_ops(OPS_EXP); return exp_f64(x); }
   // two uniforms from one block of four words
   static void two_uniforms(const uint32_t w[4], R* u1, R* u2) {
+    count_ops(2 * OPS_UNIFORM);
     *u1 = uniform_f64(w[0], w[1]);
     *u2 = uniform_f64(w[2], w[3]);
   }
@@ -255,9 +269,10 @@ struct PolicyF64 {
 };
 struct PolicyMixed {
   typedef float R;
-  static R ulog(R x) { return log_f32(x); }
-  static R uexp(R x) { return exp_f32(x); }
+  static R ulog(R x) { count_ops(OPS_LOG); return log_f32(x); }
+  static R uexp(R x) { count_ops(OPS_EXP); return exp_f32(x); }
   static void two_uniforms(const uint32_t w[4], R* u1, R* u2) {
+    count_ops(2 * OPS_UNIFORM);
     *u1 = uniform_f32(w[0]);
     *u2 = uniform_f32(w[1]);
   }
@@ -287,10 +302,12 @@ int64_t poisson_sample(typename P::R lam, typename P::R lam_thr, int kcap, const
     R p = P::uexp(-lam);
     R F = p;
     int k = 0;
+    count_ops(3);
     while (u > F && k < kcap) {
       k = k + 1;
       p = (p * lam) / (R)k;
       F = F + p;
+      count_ops(5);
     }
     return k;
   }
@@ -301,8 +318,10 @@ int64_t poisson_sample(typename P::R lam, typename P::R lam_thr, int kcap, const
   R vr = (R)0.9277 - (R)3.6224 / (b - (R)2);
   double loglam = log_f64((double)lam);
   double log_inv_alpha = log_f64((double)inv_alpha);
+  count_ops(12 + 2 * OPS_LOG);
   for (uint32_t trial = 0; trial < 64; ++trial) {
     rng.block(e, site, trial, w);
+    count_ops(14);
     R u0, v;
     P::two_uniforms(w, &u0, &v);
     R u = u0 - (R)0.5;
@@ -312,6 +331,7 @@ int64_t poisson_sample(typename P::R lam, typename P::R lam_thr, int kcap, const
     if (us >= (R)0.07 && v <= vr) return (int64_t)kf;
     if (us < (R)0.013 && v > us) continue;
     R hat = a / (us * us) + b;
+    count_ops(12 + 2 * OPS_LOG);
     double lhs = (log_f64((double)v) + log_inv_alpha) - log_f64((double)hat);
     double rhs = (-(double)lam + (double)kf * loglam) - lfact_f64((double)kf);
     if (lhs <= rhs) return (int64_t)kf;
@@ -331,6 +351,10 @@ struct Net {
                                //   4 HOR3, 5 HOR3 needs 2, 6 HOR3 needs 3
   std::vector<int> partner;    // reversible partner of each reaction, or -1
   int npairs = 0;
+  // operation-count model (see count_ops)
+  uint64_t g_cost = 0;         // evaluating all g_j from N copy numbers
+  std::vector<int> nu_nnz;     // nonzero net changes per reaction
+  uint64_t crit_cost = 0;      // L_j and the critical test for all j
 };
 
 // Validation; returns 0 on success.
@@ -374,6 +398,20 @@ int build_net(int N, int M, const int32_t* mtab, const int32_t* ptab, Net* net) 
     else if (hor == 2) c = (mult >= 2) ? 3 : 2;
     else if (hor == 3) c = (mult >= 3) ? 6 : (mult == 2 ? 5 : 4);
     net->phi_case[i] = c;
+  }
+  // Operation-count model: C(y,1) is free, C(y,2) costs 3 and C(y,3) 5
+  // operations, plus one product per factor; L_j costs two per consumed species.
+  net->g_cost = (uint64_t)N;
+  net->nu_nnz.assign(M, 0);
+  net->crit_cost = 0;
+  for (int j = 0; j < M; ++j) {
+    for (int i = 0; i < N; ++i) {
+      int mij = net->m[j * N + i];
+      if (mij > 0) net->g_cost += 1 + (mij == 1 ? 0 : (mij == 2 ? 3 : 5));
+      if (net->nu[j * N + i] != 0) net->nu_nnz[j] += 1;
+      if (net->nu[j * N + i] < 0) net->crit_cost += 2;
+    }
+    net->crit_cost += 4;
   }
   // Reversible pairs: reactions whose net change vectors are exact negatives,
   // matched greedily in ascending reaction index (reading).
@@ -458,6 +496,7 @@ typedef struct {
   double t_final;
   int64_t steps_ssa, steps_explicit, steps_implicit, rejections, newton_iters, newton_fail,
       kclip, attempts;
+  int64_t ops;  // algorithmic operation count (see count_ops)
 } orc_stats;
 
 }  // extern "C"
@@ -509,6 +548,7 @@ struct Traj {
 
   // a_j = theta_j g_j (Background section), a0 = sum in ascending j.
   void propensities() {
+    count_ops(net.g_cost + 2 * (uint64_t)M);
     g_all(x, g);
     a0 = 0;
     for (int j = 0; j < M; ++j) {
@@ -520,6 +560,7 @@ struct Traj {
   // Critical reactions (Cao 2006): L_j = min over consumed species of
   // floor(x_i / |nu_ij|); critical if a_j > 0 and L_j < n_c.
   void critical_set() {
+    count_ops(net.crit_cost);
     a0c = 0;
     for (int j = 0; j < M; ++j) {
       int64_t L = std::numeric_limits<int64_t>::max();
@@ -558,11 +599,13 @@ struct Traj {
     R eps = (R)o.eps;
     for (int i = 0; i < N; ++i) {
       if (net.phi_case[i] == 0) continue;  // not a reactant of any reaction
+      count_ops(12);
       R mu = 0, s2 = 0;
       for (int j = 0; j < M; ++j) {
         if (!use[j]) continue;
         int v = net.nu[j * N + i];
         if (v == 0) continue;
+        count_ops(4);
         mu = mu + (R)v * a[j];
         s2 = s2 + (R)(v * v) * a[j];
       }
@@ -585,6 +628,7 @@ struct Traj {
       int kk = net.partner[j];
       if (kk <= j) continue;
       if (!ncr[j] || !ncr[kk]) continue;
+      count_ops(5);
       if (std::fabs(a[j] - a[kk]) <= delta * std::min(a[j], a[kk])) {
         eq[j] = 1;
         eq[kk] = 1;
@@ -605,6 +649,7 @@ struct Traj {
     P::two_uniforms(w, &u1, &u2);
     double tau_s = (double)(-P::ulog(u1) / a0);
     double rem = t_end - t;
+    count_ops(4 + 2 * (uint64_t)M);
     if (tau_s >= rem) {  // the next firing is beyond t_end (reading: no firing)
       for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * rem;
       t = t_end;
@@ -616,6 +661,7 @@ struct Traj {
     for (int j = 0; j < M; ++j) {
       if (a[j] > (R)0) jlast = j;
       cum = cum + a[j];
+      count_ops(2);
       if (cum > thr) { jf = j; break; }
     }
     if (jf < 0) jf = jlast;
@@ -623,11 +669,14 @@ struct Traj {
     for (int i = 0; i < N; ++i) x[i] = x[i] + net.nu[jf * N + i];
     r[jf] = r[jf] + 1;
     t = t + tau_s;
+    count_ops(3 + (uint64_t)net.nu_nnz[jf]);
   }
 
   // LU with partial pivoting (first maximal |pivot|) on an n x n row-major
   // matrix, solving A z = b in place; returns false on a zero pivot.
   static bool lu_solve(int n, std::vector<double>& A, std::vector<double>& b) {
+    uint64_t nn = (uint64_t)n;
+    count_ops((2 * nn * nn * nn) / 3 + 2 * nn * nn + nn);
     for (int c = 0; c < n; ++c) {
       int piv = c;
       double best = std::fabs(A[c * n + c]);
@@ -673,9 +722,13 @@ struct Traj {
       c[i] = ci;
       y[i] = xd[i];
     }
+    count_ops((uint64_t)M + 3 * (uint64_t)N * M);
     bool converged = false;
     for (int it = 0; it < o.newton_maxit; ++it) {
       st.newton_iters += 1;
+      // residual (g(y), products, sums) and Jacobian terms of the non-critical
+      // reactions: about 5 operations per (species, species, reaction) term
+      count_ops(net.g_cost + (uint64_t)M + 5 * (uint64_t)N + 5 * (uint64_t)N * N * M / 2);
       for (int j = 0; j < M; ++j) ay[j] = ncr[j] ? theta[j] * g_of(net, j, y.data()) : 0.0;
       for (int i = 0; i < N; ++i) {
         double s = 0.0;
@@ -707,6 +760,7 @@ struct Traj {
     }
     if (!converged) { st.newton_fail += 1; return false; }
     ysol = y;
+    count_ops(net.g_cost + 5 * (uint64_t)M);
     for (int j = 0; j < M; ++j) {
       if (!ncr[j]) { k[j] = 0; continue; }
       double v = (tau * (theta[j] * g_of(net, j, y.data())) - tau * ax[j]) + (double)Pj[j];
@@ -723,6 +777,7 @@ struct Traj {
     rng.key[0] = (uint32_t)o.seed;
     rng.key[1] = (uint32_t)(o.seed >> 32) + o.rng_stream;
     rng.pid = pid;
+    g_ops = 0;
     t = o.t_start;
     e = 0;
     bool bad = false;
@@ -771,6 +826,7 @@ struct Traj {
       }
       // Leap attempts with the same propensities; tau' halves on rejection.
       for (;;) {
+        count_ops(4);
         if (tau_p < k_ssa / a0 || a0c >= a0 / k_crit) {
           // SSA burst: Cao 2006 fallback when the leap is a few SSA steps,
           // and the matLeap switch when critical reactions are fast.
@@ -814,6 +870,7 @@ struct Traj {
           for (int j = 0; j < M; ++j) {
             if (!crit[j]) continue;
             jlast = j;
+            count_ops(2);
             cum = cum + a[j];
             if (cum > thr) { jc = j; break; }
           }
@@ -828,11 +885,13 @@ struct Traj {
           last = true;
         }
         R tau_rr = (R)tau;
+        count_ops(6);
         // Poisson counts of the non-critical reactions, ascending j.
         bool overflow = false;
         for (int j = 0; j < M; ++j) {
           k[j] = 0;
           if (!ncr[j]) continue;
+          count_ops(1);
           int64_t kj = poisson_sample<P>(a[j] * tau_rr, lam_thr, kcap, rng, ea, (uint32_t)j);
           if (kj < 0) overflow = true;
           k[j] = kj;
@@ -845,6 +904,9 @@ struct Traj {
         }
         if (ok) {
           if (jc >= 0) k[jc] = 1;
+          uint64_t nnz = 0;
+          for (int j = 0; j < M; ++j) nnz += (uint64_t)net.nu_nnz[j];
+          count_ops(2 * nnz + (uint64_t)N);
           for (int i = 0; i < N; ++i) {
             int64_t v = x[i];
             for (int j = 0; j < M; ++j) v = v + (int64_t)net.nu[j * N + i] * k[j];
@@ -862,6 +924,7 @@ struct Traj {
         for (int j = 0; j < M; ++j) big = big || r[j] + k[j] > 2147483647LL;
         if (big) { status = ST_COUNT_OVERFLOW; break; }
         // Accept: trapezoid rule for G over the leap, for every reaction.
+        count_ops(net.g_cost + 5 * (uint64_t)M + (uint64_t)N + 2);
         g_all(xnew, gnew);
         for (int j = 0; j < M; ++j) {
           G[j] = G[j] + (tau * (g[j] + gnew[j])) * 0.5;
@@ -882,6 +945,7 @@ struct Traj {
     st.status = status;
     st.t_final = t;
     st.attempts = e;
+    st.ops = (int64_t)g_ops;
     if (so) *so = st;
   }
 };

@@ -1,0 +1,582 @@
+// lx_api.cpp -- host side of liblx: the C ABI of include/lx.h.
+//
+//  * network compiler: validates the flat stoichiometry table and derives the
+//    tables the kernels need (net changes, tau-bound factor cases, reversible
+//    pairs);
+//  * code generator: emits the network as compile-time constants in front of
+//    the kernel source (lx_device.h, lx_params.h, lx_sim.h, embedded at build
+//    time) and compiles it for gfx950 with hipRTC; code objects are cached in
+//    memory per (network, variant, device) and on disk by content hash;
+//  * launcher: validates arguments and enqueues the kernels on the caller's
+//    stream.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <dlfcn.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "lx.h"
+#include "lx_embedded.inc"  // lx_src_params, lx_src_device, lx_src_sim (generated)
+#include "lx_params.h"
+
+static_assert(sizeof(lx_stats) == sizeof(lx::Stats), "lx_stats layout");
+static_assert(sizeof(lx_stats) == 80, "lx_stats size");
+static_assert(sizeof(lx_options) == 152, "lx_options size");
+
+// Launchers of the static hook kernels (lx_hooks.hip).
+hipError_t lxh_launch_philox(long long, const unsigned*, const unsigned*, unsigned*, hipStream_t);
+hipError_t lxh_launch_uniform_f64(long long, const unsigned*, double*, hipStream_t);
+hipError_t lxh_launch_uniform_f32(long long, const unsigned*, float*, hipStream_t);
+hipError_t lxh_launch_math(int, long long, const void*, void*, hipStream_t);
+hipError_t lxh_launch_poisson(long long, const double*, const unsigned*, const unsigned*,
+                              const unsigned*, unsigned, unsigned, double, int, int, long long*,
+                              hipStream_t);
+hipError_t lxh_launch_exponential(long long, const unsigned*, const unsigned*, unsigned, unsigned,
+                                  int, double*, hipStream_t);
+
+namespace {
+
+thread_local std::string g_err;
+
+lx_status fail(lx_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+lx_status hip_fail(hipError_t e, const char* what) {
+  return fail(LX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+const int MAX_M = 32;
+const int MAX_N = 16;
+// The register-resident lane state needs well over 128 VGPRs; blocks of more
+// than four waves per SIMD would force spills (and were refused at dispatch),
+// so blocks are limited to 256 threads.
+const int MAX_BLOCK = 256;
+
+// ---------------------------------------------------------------------------
+// Kernel compilation and caching.
+// ---------------------------------------------------------------------------
+std::mutex g_rtc_mutex;
+
+uint64_t fnv1a(const std::string& s) {
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char c : s) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string cache_dir() {
+  const char* env = getenv("LX_KERNEL_CACHE");
+  if (env && *env) return env;
+  Dl_info info;
+  if (dladdr((void*)&fnv1a, &info) && info.dli_fname) {
+    std::string p(info.dli_fname);
+    size_t slash = p.find_last_of('/');
+    if (slash != std::string::npos) return p.substr(0, slash) + "/kcache";
+  }
+  return "";
+}
+
+const char* const RTC_OPTS[] = {"--offload-arch=gfx950",
+                                "-O3",
+                                "-std=c++17",
+                                "-ffp-contract=off",
+                                "-fhip-fp32-correctly-rounded-divide-sqrt",
+                                "-fno-gpu-flush-denormals-to-zero",
+                                "-Xclang",
+                                "-target-feature",
+                                "-Xclang",
+                                "-packed-fp32-ops"};
+
+lx_status compile_source(const std::string& src, std::vector<char>* code) {
+  std::string key = src;
+  for (const char* o : RTC_OPTS) key += std::string("\n//opt ") + o;
+  char name[32];
+  snprintf(name, sizeof(name), "%016llx.co", (unsigned long long)fnv1a(key));
+  const std::string dir = cache_dir();
+  if (!dir.empty()) {
+    std::ifstream f(dir + "/" + name, std::ios::binary);
+    if (f) {
+      std::vector<char> buf((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+      if (!buf.empty()) {
+        *code = std::move(buf);
+        return LX_OK;
+      }
+    }
+  }
+  std::lock_guard<std::mutex> lock(g_rtc_mutex);
+  hiprtcProgram prog;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "lx_sim.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+    return fail(LX_E_COMPILE, "hiprtcCreateProgram failed");
+  const int nopt = (int)(sizeof(RTC_OPTS) / sizeof(RTC_OPTS[0]));
+  hiprtcResult rc = hiprtcCompileProgram(prog, nopt, const_cast<const char**>(RTC_OPTS));
+  if (rc != HIPRTC_SUCCESS) {
+    size_t ls = 0;
+    hiprtcGetProgramLogSize(prog, &ls);
+    std::string log(ls + 1, '\0');
+    hiprtcGetProgramLog(prog, &log[0]);
+    hiprtcDestroyProgram(&prog);
+    return fail(LX_E_COMPILE, "kernel compilation failed: " + log.substr(0, 4000));
+  }
+  size_t cs = 0;
+  hiprtcGetCodeSize(prog, &cs);
+  code->assign(cs, 0);
+  hiprtcGetCode(prog, code->data());
+  hiprtcDestroyProgram(&prog);
+  if (!dir.empty()) {
+    mkdir(dir.c_str(), 0755);
+    std::string tmp = dir + "/" + name + ".tmp" + std::to_string((long long)getpid());
+    std::ofstream f(tmp, std::ios::binary);
+    if (f) {
+      f.write(code->data(), (std::streamsize)code->size());
+      f.close();
+      rename(tmp.c_str(), (dir + "/" + name).c_str());
+    }
+  }
+  return LX_OK;
+}
+
+struct Kernel {
+  hipModule_t mod = nullptr;
+  hipFunction_t fn = nullptr;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Network handle.
+// ---------------------------------------------------------------------------
+struct lx_network_s {
+  int N = 0, M = 0, npairs = 0;
+  std::vector<int> ro, nu, phi, partner;
+  std::string netsrc;
+  std::mutex mu;
+  std::map<std::string, Kernel> kernels;  // variant key -> loaded kernel
+
+  ~lx_network_s() {
+    for (auto& kv : kernels)
+      if (kv.second.mod) hipModuleUnload(kv.second.mod);
+  }
+};
+
+namespace {
+
+std::string table_src(const char* name, const std::vector<int>& v, int rows, int cols) {
+  std::ostringstream s;
+  s << "constexpr int " << name << "[" << rows << "][" << cols << "] = {";
+  for (int r = 0; r < rows; ++r) {
+    s << (r ? ",{" : "{");
+    for (int c = 0; c < cols; ++c) s << (c ? "," : "") << v[(size_t)r * cols + c];
+    s << "}";
+  }
+  s << "};\n";
+  return s.str();
+}
+
+std::string vec_src(const char* name, const std::vector<int>& v) {
+  std::ostringstream s;
+  s << "constexpr int " << name << "[" << v.size() << "] = {";
+  for (size_t q = 0; q < v.size(); ++q) s << (q ? "," : "") << v[q];
+  s << "};\n";
+  return s.str();
+}
+
+// Compile-time description of the network for the kernel source.
+std::string network_source(const lx_network_s& n) {
+  std::ostringstream s;
+  s << "namespace lxnet {\n";
+  s << "constexpr int N = " << n.N << ";\nconstexpr int M = " << n.M << ";\n";
+  s << "constexpr int NPAIRS = " << n.npairs << ";\n";
+  s << table_src("RO", n.ro, n.M, n.N);
+  s << table_src("NU", n.nu, n.M, n.N);
+  s << vec_src("PHI", n.phi);
+  s << vec_src("PARTNER", n.partner);
+  s << "}  // namespace lxnet\n";
+  return s.str();
+}
+
+// Full hipRTC source of one kernel variant of a network.
+std::string kernel_source(const lx_network_s& net, const char* variant, int precision, int block) {
+  std::ostringstream src;
+  src << "// generated by liblx\n";
+  src << "#define LX_POLICY " << (precision == LX_PREC_MIXED ? "lx::Mixed" : "lx::F64") << "\n";
+  src << "#define LX_BLOCK " << block << "\n";
+  if (strcmp(variant, "hooks") == 0) src << "#define LX_HOOKS 1\n";
+  if (strcmp(variant, "batched") == 0) src << "#define LX_BATCHED 1\n";
+  src << lx_src_params << "\n" << lx_src_device << "\n" << net.netsrc << "\n" << lx_src_sim;
+  return src.str();
+}
+
+lx_status check_device(int* dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(LX_E_UNSUPPORTED, std::string("liblx targets gfx950; device is ") + prop.gcnArchName);
+  *dev_out = dev;
+  return LX_OK;
+}
+
+// Fetch (compiling on first use) a kernel of the network for the current
+// device.  variant: "plain", "batched" or "hooks"; precision LX_PREC_*.
+lx_status get_kernel(lx_network_s* net, const char* variant, int precision, int block,
+                     const char* fname, hipFunction_t* fn) {
+  int dev = 0;
+  lx_status st = check_device(&dev);
+  if (st != LX_OK) return st;
+  std::ostringstream key;
+  key << variant << "/" << precision << "/" << block << "/" << fname << "/dev" << dev;
+  std::lock_guard<std::mutex> lock(net->mu);
+  auto it = net->kernels.find(key.str());
+  if (it != net->kernels.end()) {
+    *fn = it->second.fn;
+    return LX_OK;
+  }
+  std::vector<char> code;
+  st = compile_source(kernel_source(*net, variant, precision, block), &code);
+  if (st != LX_OK) return st;
+  Kernel k;
+  hipError_t e = hipModuleLoadData(&k.mod, code.data());
+  if (e != hipSuccess) return hip_fail(e, "hipModuleLoadData");
+  e = hipModuleGetFunction(&k.fn, k.mod, fname);
+  if (e != hipSuccess) {
+    hipModuleUnload(k.mod);
+    return hip_fail(e, "hipModuleGetFunction");
+  }
+  net->kernels[key.str()] = k;
+  *fn = k.fn;
+  return LX_OK;
+}
+
+lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, int32_t mode,
+                      lx::SimParams* prm) {
+  if (!(std::isfinite(t_end)) || !std::isfinite(o.t_start) || t_end < o.t_start)
+    return fail(LX_E_INVALID, "need finite t_start <= t_end");
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(LX_E_INVALID, "eps must be positive");
+  if (mode < 0 || mode > 2) return fail(LX_E_INVALID, "mode must be LX_MODE_*");
+  if (o.precision != LX_PREC_FP64 && o.precision != LX_PREC_MIXED)
+    return fail(LX_E_INVALID, "precision must be LX_PREC_*");
+  if (o.schedule != LX_SCHED_PLAIN && o.schedule != LX_SCHED_BATCHED)
+    return fail(LX_E_INVALID, "schedule must be LX_SCHED_*");
+  if (o.n_c < 0 || !(o.delta >= 0.0) || !(o.n_stiff > 0.0) || !(o.k_ssa >= 0.0) ||
+      !(o.k_crit > 0.0) || o.n_ssa_ex < 1 || o.n_ssa_im < 1 || !(o.lambda_thr >= 1.0) ||
+      !(o.lambda_thr <= 30.0) || !(o.newton_tol > 0.0) || o.newton_maxit < 0 ||
+      o.max_steps < 0 || o.max_steps > 4294967295LL)
+    return fail(LX_E_INVALID, "option out of range");
+  if (o.block_size != 0 && (o.block_size < 64 || o.block_size > MAX_BLOCK || o.block_size % 64 != 0))
+    return fail(LX_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
+  if ((uint64_t)o.pid_base + (uint64_t)P > 4294967296ull)
+    return fail(LX_E_INVALID, "pid_base + P exceeds 2^32 particle ids");
+  memset(prm, 0, sizeof(*prm));
+  prm->t_start = o.t_start;
+  prm->t_end = t_end;
+  prm->eps = eps;
+  prm->delta = o.delta;
+  prm->n_stiff = o.n_stiff;
+  prm->k_ssa = o.k_ssa;
+  prm->k_crit = o.k_crit;
+  prm->lam_thr = o.lambda_thr;
+  prm->newton_tol = o.newton_tol;
+  prm->max_steps = o.max_steps;
+  prm->P = P;
+  prm->k0 = (uint32_t)o.seed;
+  prm->k1 = (uint32_t)(o.seed >> 32) + o.rng_stream;
+  prm->pid_base = o.pid_base;
+  prm->n_c = o.n_c;
+  prm->n_ssa_ex = o.n_ssa_ex;
+  prm->n_ssa_im = o.n_ssa_im;
+  prm->newton_maxit = o.newton_maxit;
+  prm->kcap = 20 + 4 * (int)std::ceil(o.lambda_thr);
+  prm->mode = mode;
+  prm->accumulate = o.accumulate ? 1 : 0;
+  return LX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lx_options_default(lx_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->precision = LX_PREC_FP64;
+  o->schedule = LX_SCHED_PLAIN;
+  o->seed = 160807058ull;
+  o->n_c = 10;
+  o->delta = 0.05;
+  o->n_stiff = 100.0;
+  o->k_ssa = 10.0;
+  o->k_crit = 10.0;
+  o->n_ssa_ex = 100;
+  o->n_ssa_im = 10;
+  o->lambda_thr = 10.0;
+  o->newton_tol = 1e-10;
+  o->newton_maxit = 20;
+  o->max_steps = 10000000;
+}
+
+const char* lx_last_error(void) { return g_err.c_str(); }
+
+lx_status lx_network_create(int32_t N, int32_t M, const int32_t* ro, const int32_t* pc,
+                            lx_network* out) {
+  if (!out) return fail(LX_E_INVALID, "out is null");
+  *out = nullptr;
+  if (N < 1 || M < 1) return fail(LX_E_INVALID, "need N >= 1 and M >= 1");
+  if (!ro || !pc) return fail(LX_E_INVALID, "null stoichiometry table");
+  if (M > MAX_M || N > MAX_N)
+    return fail(LX_E_INVALID, "network too large for the register-resident kernels (M <= 32, N <= 16)");
+  lx_network_s* n = new (std::nothrow) lx_network_s();
+  if (!n) return fail(LX_E_NOMEM, "out of host memory");
+  n->N = N;
+  n->M = M;
+  n->ro.assign((size_t)M * N, 0);
+  n->nu.assign((size_t)M * N, 0);
+  std::vector<int> order(M, 0);
+  for (int j = 0; j < M; ++j) {
+    for (int i = 0; i < N; ++i) {
+      const int m = ro[(size_t)j * N + i], p = pc[(size_t)j * N + i];
+      if (m < 0 || p < 0 || m > 3 || p > 1000000) {
+        delete n;
+        return fail(LX_E_INVALID, "table entries must be >= 0 (reactant orders <= 3)");
+      }
+      n->ro[(size_t)j * N + i] = m;
+      n->nu[(size_t)j * N + i] = p - m;
+      order[j] += m;
+    }
+    if (order[j] > 3) {
+      delete n;
+      return fail(LX_E_INVALID, "reaction order above 3");
+    }
+  }
+  // Tau-bound factor case per species: highest order of the reactions that
+  // consume it, and the largest multiplicity among those reactions.
+  n->phi.assign(N, 0);
+  for (int i = 0; i < N; ++i) {
+    int hor = 0, mult = 0;
+    for (int j = 0; j < M; ++j) {
+      const int m = n->ro[(size_t)j * N + i];
+      if (!m) continue;
+      if (order[j] > hor) {
+        hor = order[j];
+        mult = m;
+      } else if (order[j] == hor && m > mult) {
+        mult = m;
+      }
+    }
+    int c = 0;
+    if (hor == 1) c = 1;
+    else if (hor == 2) c = mult >= 2 ? 3 : 2;
+    else if (hor == 3) c = mult >= 3 ? 6 : (mult == 2 ? 5 : 4);
+    n->phi[i] = c;
+  }
+  // Reversible pairs: exactly opposite net changes, greedy by ascending index.
+  n->partner.assign(M, -1);
+  for (int j = 0; j < M; ++j) {
+    if (n->partner[j] >= 0) continue;
+    bool nz = false;
+    for (int i = 0; i < N; ++i) nz = nz || n->nu[(size_t)j * N + i] != 0;
+    if (!nz) continue;
+    for (int k = j + 1; k < M; ++k) {
+      if (n->partner[k] >= 0) continue;
+      bool opp = true;
+      for (int i = 0; i < N && opp; ++i) opp = n->nu[(size_t)k * N + i] == -n->nu[(size_t)j * N + i];
+      if (opp) {
+        n->partner[j] = k;
+        n->partner[k] = j;
+        n->npairs += 1;
+        break;
+      }
+    }
+  }
+  n->netsrc = network_source(*n);
+  *out = n;
+  return LX_OK;
+}
+
+lx_status lx_network_prepare(lx_network net, int32_t precision, int32_t schedule,
+                             int32_t block_size) {
+  if (!net) return fail(LX_E_INVALID, "null network");
+  if (precision != LX_PREC_FP64 && precision != LX_PREC_MIXED)
+    return fail(LX_E_INVALID, "precision must be LX_PREC_*");
+  if (schedule != LX_SCHED_PLAIN && schedule != LX_SCHED_BATCHED)
+    return fail(LX_E_INVALID, "schedule must be LX_SCHED_*");
+  if (block_size != 0 && (block_size < 64 || block_size > MAX_BLOCK || block_size % 64 != 0))
+    return fail(LX_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
+  const int block = block_size ? block_size : 64;
+  std::vector<char> code;
+  return compile_source(
+      kernel_source(*net, schedule == LX_SCHED_BATCHED ? "batched" : "plain", precision, block),
+      &code);
+}
+
+lx_status lx_network_destroy(lx_network net) {
+  delete net;
+  return LX_OK;
+}
+
+lx_status lx_network_info(lx_network net, int32_t* N, int32_t* M, int32_t* n_pairs) {
+  if (!net) return fail(LX_E_INVALID, "null network");
+  if (N) *N = net->N;
+  if (M) *M = net->M;
+  if (n_pairs) *n_pairs = net->npairs;
+  return LX_OK;
+}
+
+lx_status lx_simulate(lx_network net, int64_t P, const double* theta, const int32_t* x0,
+                      double t_end, double eps, int32_t mode, const lx_options* opt,
+                      int32_t* x_out, int32_t* r_out, double* G_out, lx_stats* stats,
+                      void* stream) {
+  if (!net) return fail(LX_E_INVALID, "null network");
+  if (P < 0) return fail(LX_E_INVALID, "P < 0");
+  lx_options o;
+  if (opt) o = *opt;
+  else lx_options_default(&o);
+  lx::SimParams prm;
+  lx_status st = fill_params(o, P, t_end, eps, mode, &prm);
+  if (st != LX_OK) return st;
+  if (P == 0) return LX_OK;
+  if (!theta || !x0 || !x_out || !r_out || !G_out)
+    return fail(LX_E_INVALID, "null input/output pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const int block = o.block_size ? o.block_size : 64;
+  hipFunction_t fn;
+  st = get_kernel(net, "plain", o.precision, block, "lx_sim_plain", &fn);
+  if (st != LX_OK) return st;
+  const long long grid = (P + block - 1) / block;
+  if (grid > 0x7fffffffLL) return fail(LX_E_INVALID, "P too large for one launch");
+  lx::Stats* sp = (lx::Stats*)stats;
+  void* args[] = {(void*)&theta, (void*)&x0, (void*)&x_out, (void*)&r_out,
+                  (void*)&G_out, (void*)&sp, (void*)&prm};
+  hipError_t e = hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0, s,
+                                       args, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "launch lx_sim_plain");
+  return LX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Test hooks.
+// ---------------------------------------------------------------------------
+lx_status lx_test_philox(int64_t n, const uint32_t* ctr, const uint32_t* key, uint32_t* out,
+                         void* stream) {
+  if (n < 0 || (n > 0 && (!ctr || !key || !out))) return fail(LX_E_INVALID, "bad arguments");
+  if (n == 0) return LX_OK;
+  hipError_t e = lxh_launch_philox(n, ctr, key, out, (hipStream_t)stream);
+  return e == hipSuccess ? LX_OK : hip_fail(e, "philox hook");
+}
+
+lx_status lx_test_uniform_f64(int64_t n, const uint32_t* w, double* out, void* stream) {
+  if (n < 0 || (n > 0 && (!w || !out))) return fail(LX_E_INVALID, "bad arguments");
+  if (n == 0) return LX_OK;
+  hipError_t e = lxh_launch_uniform_f64(n, w, out, (hipStream_t)stream);
+  return e == hipSuccess ? LX_OK : hip_fail(e, "uniform hook");
+}
+
+lx_status lx_test_uniform_f32(int64_t n, const uint32_t* w, float* out, void* stream) {
+  if (n < 0 || (n > 0 && (!w || !out))) return fail(LX_E_INVALID, "bad arguments");
+  if (n == 0) return LX_OK;
+  hipError_t e = lxh_launch_uniform_f32(n, w, out, (hipStream_t)stream);
+  return e == hipSuccess ? LX_OK : hip_fail(e, "uniform hook");
+}
+
+lx_status lx_test_math(int32_t fn, int64_t n, const void* in, void* out, void* stream) {
+  const bool ok_fn = (fn >= 0 && fn <= 3) || (fn >= 10 && fn <= 12);
+  if (!ok_fn || n < 0 || (n > 0 && (!in || !out))) return fail(LX_E_INVALID, "bad arguments");
+  if (n == 0) return LX_OK;
+  hipError_t e = lxh_launch_math(fn, n, in, out, (hipStream_t)stream);
+  return e == hipSuccess ? LX_OK : hip_fail(e, "math hook");
+}
+
+lx_status lx_test_poisson(int64_t n, const double* lam, const uint32_t* pid, const uint32_t* e,
+                          const uint32_t* site, uint64_t seed, uint32_t stream_id,
+                          double lambda_thr, int32_t precision, int64_t* out, void* stream) {
+  if (n < 0 || (n > 0 && (!lam || !pid || !e || !site || !out)) || !(lambda_thr >= 1.0) ||
+      !(lambda_thr <= 30.0) || (precision != LX_PREC_FP64 && precision != LX_PREC_MIXED))
+    return fail(LX_E_INVALID, "bad arguments");
+  if (n == 0) return LX_OK;
+  const int kcap = 20 + 4 * (int)std::ceil(lambda_thr);
+  hipError_t err = lxh_launch_poisson(n, lam, pid, e, site, (uint32_t)seed,
+                                      (uint32_t)(seed >> 32) + stream_id, lambda_thr, kcap,
+                                      precision == LX_PREC_MIXED, (long long*)out,
+                                      (hipStream_t)stream);
+  return err == hipSuccess ? LX_OK : hip_fail(err, "poisson hook");
+}
+
+lx_status lx_test_exponential(int64_t n, const uint32_t* pid, const uint32_t* e, uint64_t seed,
+                              uint32_t stream_id, int32_t precision, double* out, void* stream) {
+  if (n < 0 || (n > 0 && (!pid || !e || !out)) ||
+      (precision != LX_PREC_FP64 && precision != LX_PREC_MIXED))
+    return fail(LX_E_INVALID, "bad arguments");
+  if (n == 0) return LX_OK;
+  hipError_t err = lxh_launch_exponential(n, pid, e, (uint32_t)seed,
+                                          (uint32_t)(seed >> 32) + stream_id,
+                                          precision == LX_PREC_MIXED, out, (hipStream_t)stream);
+  return err == hipSuccess ? LX_OK : hip_fail(err, "exponential hook");
+}
+
+lx_status lx_test_tau_select(lx_network net, int64_t Q, const double* theta, const int32_t* x,
+                             double eps, int32_t mode, const lx_options* opt, double* a,
+                             uint32_t* crit, uint32_t* eq, double* tau, int32_t* action,
+                             void* stream) {
+  if (!net || Q < 0) return fail(LX_E_INVALID, "bad arguments");
+  lx_options o;
+  if (opt) o = *opt;
+  else lx_options_default(&o);
+  lx::SimParams prm;
+  lx_status st = fill_params(o, Q, 1.0 + o.t_start, eps, mode, &prm);
+  if (st != LX_OK) return st;
+  if (Q == 0) return LX_OK;
+  if (!theta || !x || !a || !crit || !eq || !tau || !action)
+    return fail(LX_E_INVALID, "null pointer");
+  hipFunction_t fn;
+  st = get_kernel(net, "hooks", o.precision, 64, "lx_hook_tau", &fn);
+  if (st != LX_OK) return st;
+  void* args[] = {(void*)&theta, (void*)&x, (void*)&a, (void*)&crit, (void*)&eq,
+                  (void*)&tau, (void*)&action, (void*)&prm};
+  hipError_t e = hipModuleLaunchKernel(fn, (unsigned)((Q + 63) / 64), 1, 1, 64, 1, 1, 0,
+                                       (hipStream_t)stream, args, nullptr);
+  return e == hipSuccess ? LX_OK : hip_fail(e, "tau hook");
+}
+
+lx_status lx_test_implicit(lx_network net, int64_t Q, const double* theta, const int32_t* x,
+                           const double* tau, const int64_t* Pj, const int32_t* jc,
+                           const lx_options* opt, int64_t* k, int32_t* ok, int32_t* iters,
+                           void* stream) {
+  if (!net || Q < 0) return fail(LX_E_INVALID, "bad arguments");
+  lx_options o;
+  if (opt) o = *opt;
+  else lx_options_default(&o);
+  lx::SimParams prm;
+  lx_status st = fill_params(o, Q, 1.0 + o.t_start, 0.03, 0, &prm);
+  if (st != LX_OK) return st;
+  if (Q == 0) return LX_OK;
+  if (!theta || !x || !tau || !Pj || !jc || !k || !ok || !iters)
+    return fail(LX_E_INVALID, "null pointer");
+  hipFunction_t fn;
+  st = get_kernel(net, "hooks", LX_PREC_FP64, 64, "lx_hook_implicit", &fn);
+  if (st != LX_OK) return st;
+  void* args[] = {(void*)&theta, (void*)&x, (void*)&tau, (void*)&Pj, (void*)&jc,
+                  (void*)&k, (void*)&ok, (void*)&iters, (void*)&prm};
+  hipError_t e = hipModuleLaunchKernel(fn, (unsigned)((Q + 63) / 64), 1, 1, 64, 1, 1, 0,
+                                       (hipStream_t)stream, args, nullptr);
+  return e == hipSuccess ? LX_OK : hip_fail(e, "implicit hook");
+}
+
+}  // extern "C"

@@ -1,0 +1,285 @@
+// lx_device.h -- device building blocks of the ensemble tau-leaping kernels:
+// counter-based RNG, uniform maps, elementary functions and the samplers.
+//
+// This header is compiled twice: statically by hipcc (test-hook kernels in
+// lx_hooks.hip) and at run time by hipRTC, where it is prepended to the
+// network-specialised simulation source.  It therefore includes nothing and
+// uses only compiler builtins.
+//
+// Floating point: compiled with -ffp-contract=off; every fused multiply-add is
+// an explicit __builtin_fma.  Division and square root are the correctly
+// rounded IEEE operations in both precisions.  The operation sequences below
+// are fixed so that results are reproducible bit for bit.
+#pragma once
+
+namespace lx {
+
+typedef unsigned int u32;
+typedef unsigned long long u64;
+
+#define LX_INF_F64 __builtin_inf()
+#define LX_INF_F32 __builtin_inff()
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// and xors with a Weyl-sequence key schedule.  Output is a pure function of
+// (counter, key).
+// ---------------------------------------------------------------------------
+struct Words4 {
+  u32 w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words4 philox(u32 c0, u32 c1, u32 c2, u32 c3, u32 k0, u32 k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const u64 p0 = (u64)0xD2511F53u * (u64)c0;
+    const u64 p1 = (u64)0xCD9E8D57u * (u64)c2;
+    const u32 n0 = (u32)(p1 >> 32) ^ c1 ^ k0;
+    const u32 n2 = (u32)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (u32)p1;
+    c3 = (u32)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  Words4 o;
+  o.w0 = c0;
+  o.w1 = c1;
+  o.w2 = c2;
+  o.w3 = c3;
+  return o;
+}
+
+// Draw-site addressing: counter = (particle id, attempt e, site, trial).
+constexpr u32 SITE_CRIT = 0x40000000u;
+constexpr u32 SITE_SSA = 0x40000001u;
+
+struct Key {
+  u32 k0, k1;
+};
+
+__device__ __forceinline__ Words4 draw_block(const Key& key, u32 pid, u32 e, u32 site, u32 trial) {
+  return philox(pid, e, site, trial, key.k0, key.k1);
+}
+
+// Open-interval uniforms, exact by construction.
+__device__ __forceinline__ float uniform_f32(u32 w) {
+  return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+}
+__device__ __forceinline__ double uniform_f64(u32 hi, u32 lo) {
+  return ((double)(hi >> 6) * 67108864.0 + (double)(lo >> 6) + 0.5) * 0x1p-52;
+}
+
+// ---------------------------------------------------------------------------
+// Elementary functions.
+//   exp: x = k ln2 + r (Cody-Waite, ln2 split so k*LN2_HI is exact),
+//        e^r by its Taylor polynomial in Horner form, times 2^k.
+//   log: x = 2^e m, m in [sqrt(1/2), sqrt(2)), f = m - 1, s = f / (2 + f);
+//        log(1 + f) = f - f^2/2 + s (f^2/2 + R(s^2)) with R the tail of the
+//        atanh series, plus e ln2 in two parts.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp_f64(double x) {
+  if (x != x) return x;
+  if (x > 709.782712893384) return LX_INF_F64;
+  if (x < -745.2) return 0.0;
+  const double kd = __builtin_floor(x * 0x1.71547652b82fep0 + 0.5);
+  const double hi = x - kd * 0x1.62e42feep-1;
+  const double r = hi - kd * 0x1.a39ef35793c76p-33;
+  double p = 1.0 / 6227020800.0;
+  p = __builtin_fma(p, r, 1.0 / 479001600.0);
+  p = __builtin_fma(p, r, 1.0 / 39916800.0);
+  p = __builtin_fma(p, r, 1.0 / 3628800.0);
+  p = __builtin_fma(p, r, 1.0 / 362880.0);
+  p = __builtin_fma(p, r, 1.0 / 40320.0);
+  p = __builtin_fma(p, r, 1.0 / 5040.0);
+  p = __builtin_fma(p, r, 1.0 / 720.0);
+  p = __builtin_fma(p, r, 1.0 / 120.0);
+  p = __builtin_fma(p, r, 1.0 / 24.0);
+  p = __builtin_fma(p, r, 1.0 / 6.0);
+  p = __builtin_fma(p, r, 0.5);
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return __builtin_amdgcn_ldexp(p, (int)kd);
+}
+
+__device__ __forceinline__ double log_f64(double x) {
+  if (!(x > 0.0)) return x == 0.0 ? -LX_INF_F64 : __builtin_nan("");
+  if (x == LX_INF_F64) return x;
+  double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
+  int e = __builtin_amdgcn_frexp_exp(x);
+  if (m < 0x1.6a09e667f3bcdp-1) {
+    m = m + m;
+    e = e - 1;
+  }
+  const double f = m - 1.0;
+  const double hfsq = (0.5 * f) * f;
+  const double s = f / (2.0 + f);
+  const double z = s * s;
+  double q = 2.0 / 21.0;
+  q = __builtin_fma(q, z, 2.0 / 19.0);
+  q = __builtin_fma(q, z, 2.0 / 17.0);
+  q = __builtin_fma(q, z, 2.0 / 15.0);
+  q = __builtin_fma(q, z, 2.0 / 13.0);
+  q = __builtin_fma(q, z, 2.0 / 11.0);
+  q = __builtin_fma(q, z, 2.0 / 9.0);
+  q = __builtin_fma(q, z, 2.0 / 7.0);
+  q = __builtin_fma(q, z, 2.0 / 5.0);
+  q = __builtin_fma(q, z, 2.0 / 3.0);
+  const double R = z * q;
+  const double ed = (double)e;
+  return ed * 0x1.62e42feep-1 - ((hfsq - (s * (hfsq + R) + ed * 0x1.a39ef35793c76p-33)) - f);
+}
+
+__device__ __forceinline__ float exp_f32(float x) {
+  if (x != x) return x;
+  if (x > 88.72283f) return LX_INF_F32;
+  if (x < -103.9721f) return 0.0f;
+  const float kf = __builtin_floorf(x * 0x1.715476p0f + 0.5f);
+  const float hi = x - kf * 0x1.62e4p-1f;
+  const float r = hi - kf * 0x1.7f7d1cp-20f;
+  float p = 1.0f / 5040.0f;
+  p = __builtin_fmaf(p, r, 1.0f / 720.0f);
+  p = __builtin_fmaf(p, r, 1.0f / 120.0f);
+  p = __builtin_fmaf(p, r, 1.0f / 24.0f);
+  p = __builtin_fmaf(p, r, 1.0f / 6.0f);
+  p = __builtin_fmaf(p, r, 0.5f);
+  p = __builtin_fmaf(p, r, 1.0f);
+  p = __builtin_fmaf(p, r, 1.0f);
+  return __builtin_amdgcn_ldexpf(p, (int)kf);
+}
+
+__device__ __forceinline__ float log_f32(float x) {
+  if (!(x > 0.0f)) return x == 0.0f ? -LX_INF_F32 : __builtin_nanf("");
+  if (x == LX_INF_F32) return x;
+  float m = __builtin_amdgcn_frexp_mantf(x);
+  int e = __builtin_amdgcn_frexp_expf(x);
+  if (m < 0x1.6a09e6p-1f) {
+    m = m + m;
+    e = e - 1;
+  }
+  const float f = m - 1.0f;
+  const float hfsq = (0.5f * f) * f;
+  const float s = f / (2.0f + f);
+  const float z = s * s;
+  float q = 2.0f / 11.0f;
+  q = __builtin_fmaf(q, z, 2.0f / 9.0f);
+  q = __builtin_fmaf(q, z, 2.0f / 7.0f);
+  q = __builtin_fmaf(q, z, 2.0f / 5.0f);
+  q = __builtin_fmaf(q, z, 2.0f / 3.0f);
+  const float R = z * q;
+  const float ef = (float)e;
+  return ef * 0x1.62e4p-1f - ((hfsq - (s * (hfsq + R) + ef * 0x1.7f7d1cp-20f)) - f);
+}
+
+// log(k!) for integer-valued k >= 0: exact product for k <= 17, Stirling's
+// series for log Gamma(k + 1) with four correction terms above.
+__device__ __noinline__ double lfact_f64(double k) {
+  if (k <= 17.0) {
+    double prod = 1.0;
+    for (double i = 2.0; i <= k; i = i + 1.0) prod = prod * i;
+    return log_f64(prod);
+  }
+  const double n = k + 1.0;
+  const double rn = 1.0 / n;
+  const double rn2 = rn * rn;
+  const double corr =
+      rn * (1.0 / 12.0 - rn2 * (1.0 / 360.0 - rn2 * (1.0 / 1260.0 - rn2 * (1.0 / 1680.0))));
+  return ((k + 0.5) * log_f64(n) - n) + 0x1.d67f1c864beb5p-1 + corr;
+}
+
+// ---------------------------------------------------------------------------
+// Precision policies.  R is the type of propensities, tau bounds, Poisson
+// means and sampler arithmetic; time, G and the implicit solve are double.
+// ---------------------------------------------------------------------------
+struct F64 {
+  typedef double R;
+  static constexpr bool mixed = false;
+  __device__ static __forceinline__ R ulog(R v) { return log_f64(v); }
+  __device__ static __forceinline__ R uexp(R v) { return exp_f64(v); }
+  __device__ static __forceinline__ R sqrt_(R v) { return __builtin_sqrt(v); }
+  __device__ static __forceinline__ R floor_(R v) { return __builtin_floor(v); }
+  __device__ static __forceinline__ R fabs_(R v) { return __builtin_fabs(v); }
+  __device__ static __forceinline__ void uniforms(const Words4& w, R* u1, R* u2) {
+    *u1 = uniform_f64(w.w0, w.w1);
+    *u2 = uniform_f64(w.w2, w.w3);
+  }
+  __device__ static __forceinline__ double lambda_max() { return 1073741824.0; }
+  __device__ static __forceinline__ R inf() { return LX_INF_F64; }
+};
+
+struct Mixed {
+  typedef float R;
+  static constexpr bool mixed = true;
+  __device__ static __forceinline__ R ulog(R v) { return log_f32(v); }
+  __device__ static __forceinline__ R uexp(R v) { return exp_f32(v); }
+  __device__ static __forceinline__ R sqrt_(R v) { return __builtin_sqrtf(v); }
+  __device__ static __forceinline__ R floor_(R v) { return __builtin_floorf(v); }
+  __device__ static __forceinline__ R fabs_(R v) { return __builtin_fabsf(v); }
+  __device__ static __forceinline__ void uniforms(const Words4& w, R* u1, R* u2) {
+    *u1 = uniform_f32(w.w0);
+    *u2 = uniform_f32(w.w1);
+  }
+  __device__ static __forceinline__ double lambda_max() { return 4194304.0; }
+  __device__ static __forceinline__ R inf() { return LX_INF_F32; }
+};
+
+// ---------------------------------------------------------------------------
+// Poisson sampler: inversion below lam_thr (one uniform), PTRS of Hoermann
+// (1993) above (one (U, V) pair per round, final log-density test in double).
+// Returns -1 when lam is beyond the policy's range.
+// ---------------------------------------------------------------------------
+template <class P>
+__device__ __noinline__ long long poisson_ptrs(typename P::R lam, const Key& key, u32 pid, u32 e,
+                                               u32 site) {
+  typedef typename P::R R;
+  const R slam = P::sqrt_(lam);
+  const R b = (R)0.931 + (R)2.53 * slam;
+  const R a = (R)-0.059 + (R)0.02483 * b;
+  const R inv_alpha = (R)1.1239 + (R)1.1328 / (b - (R)3.4);
+  const R vr = (R)0.9277 - (R)3.6224 / (b - (R)2);
+  const double loglam = log_f64((double)lam);
+  const double log_inv_alpha = log_f64((double)inv_alpha);
+  for (u32 trial = 0; trial < 64; ++trial) {
+    const Words4 w = draw_block(key, pid, e, site, trial);
+    R u0, v;
+    P::uniforms(w, &u0, &v);
+    const R u = u0 - (R)0.5;
+    const R us = (R)0.5 - P::fabs_(u);
+    const R kf = P::floor_((((R)2 * a) / us + b) * u + lam + (R)0.43);
+    if (kf < (R)0 || (double)kf > 1073741824.0) continue;
+    if (us >= (R)0.07 && v <= vr) return (long long)kf;
+    if (us < (R)0.013 && v > us) continue;
+    const R hat = a / (us * us) + b;
+    const double lhs = (log_f64((double)v) + log_inv_alpha) - log_f64((double)hat);
+    const double rhs = (-(double)lam + (double)kf * loglam) - lfact_f64((double)kf);
+    if (lhs <= rhs) return (long long)kf;
+  }
+  return (long long)__builtin_floor((double)lam);
+}
+
+template <class P>
+__device__ __forceinline__ long long poisson_sample(typename P::R lam, typename P::R lam_thr,
+                                                    int kcap, const Key& key, u32 pid, u32 e,
+                                                    u32 site) {
+  typedef typename P::R R;
+  if (!(lam > (R)0)) return 0;
+  if ((double)lam > P::lambda_max()) return -1;
+  if (lam < lam_thr) {
+    const Words4 w = draw_block(key, pid, e, site, 0);
+    R u, unused;
+    P::uniforms(w, &u, &unused);
+    R p = P::uexp(-lam);
+    R F = p;
+    int k = 0;
+    while (u > F && k < kcap) {
+      k = k + 1;
+      p = (p * lam) / (R)k;
+      F = F + p;
+    }
+    return k;
+  }
+  return poisson_ptrs<P>(lam, key, pid, e, site);
+}
+
+}  // namespace lx

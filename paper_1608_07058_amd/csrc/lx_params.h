@@ -1,0 +1,40 @@
+// lx_params.h -- plain-data structures shared by the host library and the
+// kernels it compiles at run time (no includes, no HIP types).
+#pragma once
+
+namespace lx {
+
+enum Mode { MODE_ADAPTIVE = 0, MODE_EXPLICIT = 1, MODE_SSA = 2 };
+
+// Per-trajectory status (lx_stats.status).
+enum LaneStatus {
+  LANE_OK = 0,
+  LANE_STEP_BUDGET = 1,      // max_steps attempts used before t_end
+  LANE_LAMBDA_OVERFLOW = 2,  // a Poisson mean beyond the sampler's range
+  LANE_BAD_INPUT = 3,        // negative or non-finite theta, negative x0
+  LANE_COUNT_OVERFLOW = 4    // a copy number or firing count beyond int32
+};
+
+// Kernel parameters, passed by value.
+struct SimParams {
+  double t_start, t_end;
+  double eps, delta, n_stiff, k_ssa, k_crit, lam_thr, newton_tol;
+  long long max_steps;
+  long long P;
+  unsigned int k0, k1, pid_base;
+  int n_c, n_ssa_ex, n_ssa_im, newton_maxit, kcap, mode, accumulate;
+  // batched scheduler
+  unsigned int* cursor;   // global particle cursor (work stealing), or null
+  int chunk;              // particles taken per cursor increment
+  int regroup;            // regroup interval in loop iterations (0: never)
+};
+
+// Per-trajectory statistics (layout of the public lx_stats).
+struct Stats {
+  int status, pad;
+  double t_final;
+  long long steps_ssa, steps_explicit, steps_implicit, rejections, newton_iters, newton_fail,
+      kclip, attempts;
+};
+
+}  // namespace lx

@@ -1,0 +1,681 @@
+// lx_sim.h -- network-specialised simulation of one trajectory per lane.
+//
+// Compiled at run time by hipRTC after lx_device.h, lx_params.h and a
+// generated block that defines namespace lxnet:
+//   N, M         species and reactions (M <= 32 here)
+//   RO[M][N]     reactant orders m_ij
+//   NU[M][N]     net changes nu_ij = p_ij - m_ij
+//   PHI[N]       case of the tau-bound factor of each species (0: not a reactant)
+//   PARTNER[M]   reversible partner reaction or -1;  NPAIRS
+// Every loop over species or reactions has a compile-time trip count and is
+// unrolled, so per-lane state lives in registers and the tables fold into
+// immediate operands.
+//
+// The method (matLeap, arXiv 1608.07058): a_j = theta_j g_j(X) and the
+// statistics r_j (firings), G_j = integral of g_j (trapezoid while leaping,
+// exact during SSA) -- Background section; adaptive explicit/implicit leaping
+// with critical reactions, the partial-equilibrium implicit switch and the
+// switch to SSA when critical reactions are fast -- Implementation section;
+// tau bounded by the relative-change rule of Cao et al. 2006 -- Background.
+#pragma once
+
+namespace lx {
+
+using lxnet::M;
+using lxnet::N;
+
+static_assert(M <= 32, "reaction masks are 32-bit");
+
+__device__ __forceinline__ double binom_real(double y, int mult) {
+  if (mult == 1) return y;
+  if (mult == 2) return (y * (y - 1.0)) * 0.5;
+  return ((y * (y - 1.0)) * (y - 2.0)) / 6.0;
+}
+
+__device__ __forceinline__ double binom_real_deriv(double y, int mult) {
+  if (mult == 1) return 1.0;
+  if (mult == 2) return y - 0.5;
+  return ((3.0 * y - 6.0) * y + 2.0) / 6.0;
+}
+
+// g_j(y) = prod over reactant species (ascending) of C(y_i, m_ij).
+__device__ __forceinline__ void g_all(const double (&y)[N], double (&g)[M]) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double gj = 1.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (lxnet::RO[j][i] > 0) gj = gj * binom_real(y[i], lxnet::RO[j][i]);
+    g[j] = gj;
+  }
+}
+
+// d g_j / d y_k.
+__device__ __forceinline__ double dg_of(int j, int k, const double (&y)[N]) {
+  double gj = 1.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (lxnet::RO[j][i] == 0) continue;
+    gj = gj * (i == k ? binom_real_deriv(y[i], lxnet::RO[j][i]) : binom_real(y[i], lxnet::RO[j][i]));
+  }
+  return gj;
+}
+
+template <class P>
+struct Lane {
+  typedef typename P::R R;
+
+  // particle state
+  u32 pid;
+  double th[M];
+  R thr[M];
+  int x[N];
+  int r[M];
+  double G[M];
+  double t;
+  u32 e;
+  int status;
+  // step state
+  double g[M];
+  R a[M];
+  R a0, a0c;
+  u32 crit, ncr;  // reaction bitmasks
+  bool plan, gvalid, implicit;
+  R tau_p;
+  int ssa_left;
+  // counters
+  long long n_ssa, n_ex, n_im, n_rej, n_nit, n_nfail, n_clip;
+
+  __device__ __forceinline__ bool active(const SimParams& prm) const {
+    return status == LANE_OK && t < prm.t_end;
+  }
+
+  __device__ __forceinline__ void load(long long p, const double* __restrict__ theta,
+                                       const int* __restrict__ x0, const int* r_in,
+                                       const double* G_in, const SimParams& prm) {
+    pid = prm.pid_base + (u32)p;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      th[j] = theta[p * M + j];
+      thr[j] = (R)th[j];
+      bad = bad || !(th[j] >= 0.0) || th[j] == LX_INF_F64;
+      r[j] = prm.accumulate ? r_in[p * M + j] : 0;
+      G[j] = prm.accumulate ? G_in[p * M + j] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      x[i] = x0[p * N + i];
+      bad = bad || x[i] < 0;
+    }
+    status = bad ? LANE_BAD_INPUT : LANE_OK;
+    t = prm.t_start;
+    e = 0;
+    plan = false;
+    gvalid = false;
+    implicit = false;
+    ssa_left = 0;
+    n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = 0;
+  }
+
+  __device__ __forceinline__ void store(long long p, int* x_out, int* r_out, double* G_out,
+                                        Stats* stats) const {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x_out[p * N + i] = x[i];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      r_out[p * M + j] = r[j];
+      G_out[p * M + j] = G[j];
+    }
+    if (stats) {
+      Stats s;
+      s.status = status;
+      s.pad = 0;
+      s.t_final = t;
+      s.steps_ssa = n_ssa;
+      s.steps_explicit = n_ex;
+      s.steps_implicit = n_im;
+      s.rejections = n_rej;
+      s.newton_iters = n_nit;
+      s.newton_fail = n_nfail;
+      s.kclip = n_clip;
+      s.attempts = e;
+      stats[p] = s;
+    }
+  }
+
+  // a_j = theta_j g_j (Background section); a0 summed in ascending j.
+  __device__ __forceinline__ void propensities() {
+    if (!gvalid) {
+      double xd[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) xd[i] = (double)x[i];
+      g_all(xd, g);
+      gvalid = true;
+    }
+    a0 = (R)0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      a[j] = thr[j] * (R)g[j];
+      a0 = a0 + a[j];
+    }
+  }
+
+  // Factor phi_i of the highest-order reaction of species i (Cao 2006).
+  __device__ __forceinline__ R phi(int i) const {
+    const int c = lxnet::PHI[i];
+    if (c == 1) return (R)1;
+    if (c == 2) return (R)2;
+    if (c == 4) return (R)3;
+    const R xm1 = (R)(x[i] - 1 > 1 ? x[i] - 1 : 1);
+    if (c == 3) return (R)2 + (R)1 / xm1;
+    if (c == 5) return (R)1.5 * ((R)2 + (R)1 / xm1);
+    const R xm2 = (R)(x[i] - 2 > 1 ? x[i] - 2 : 1);
+    return ((R)3 + (R)1 / xm1) + (R)2 / xm2;
+  }
+
+  // Tau selection over the reaction mask `use` (Cao 2006): bound the expected
+  // change and variance of every reactant species by max(eps x_i/phi_i, 1).
+  __device__ __forceinline__ R tau_select(u32 use, R eps) const {
+    R tau = P::inf();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (lxnet::PHI[i] == 0) continue;
+      R mu = (R)0, s2 = (R)0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const int v = lxnet::NU[j][i];
+        if (v == 0) continue;
+        if ((use >> j) & 1u) {
+          mu = mu + (R)v * a[j];
+          s2 = s2 + (R)(v * v) * a[j];
+        }
+      }
+      R num = eps * (R)x[i];
+      if (lxnet::PHI[i] != 1) num = num / phi(i);
+      const R bound = num < (R)1 ? (R)1 : num;
+      const R t1 = (mu != (R)0) ? bound / P::fabs_(mu) : P::inf();
+      const R t2 = (s2 != (R)0) ? (bound * bound) / s2 : P::inf();
+      const R ti = t2 < t1 ? t2 : t1;
+      tau = ti < tau ? ti : tau;
+    }
+    return tau;
+  }
+
+  // Critical set, tau_ex, partial equilibrium, tau_im and the leap type.
+  __device__ __forceinline__ void make_plan(const SimParams& prm) {
+    R tau_ex, tau_im;
+    u32 eq;
+    decide(prm, &tau_ex, &tau_im, &eq);
+  }
+
+  __device__ __forceinline__ void decide(const SimParams& prm, R* tau_ex_out, R* tau_im_out,
+                                         u32* eq_out) {
+    crit = 0;
+    ncr = 0;
+    a0c = (R)0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      int L = 0x7fffffff;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int v = lxnet::NU[j][i];
+        if (v < 0) {
+          const int q = x[i] / (-v);
+          L = q < L ? q : L;
+        }
+      }
+      const bool pos = a[j] > (R)0;
+      const bool c = pos && L < prm.n_c;
+      crit |= (c ? 1u : 0u) << j;
+      ncr |= ((pos && !c) ? 1u : 0u) << j;
+      if (c) a0c = a0c + a[j];
+    }
+    const R eps = (R)prm.eps;
+    const R tau_ex = tau_select(ncr, eps);
+    implicit = false;
+    tau_p = tau_ex;
+    *tau_ex_out = tau_ex;
+    *tau_im_out = P::inf();
+    *eq_out = 0;
+    if (lxnet::NPAIRS > 0 && prm.mode == MODE_ADAPTIVE) {
+      u32 eq = 0;
+      const R delta = (R)prm.delta;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const int k = lxnet::PARTNER[j];
+        if (k <= j) continue;
+        if (((ncr >> j) & 1u) && ((ncr >> k) & 1u)) {
+          const R lo = a[k] < a[j] ? a[k] : a[j];
+          if (P::fabs_(a[j] - a[k]) <= delta * lo) eq |= (1u << j) | (1u << k);
+        }
+      }
+      *eq_out = eq;
+      if (eq) {
+        const R tau_im = tau_select(ncr & ~eq, eps);
+        *tau_im_out = tau_im;
+        if (tau_im > (R)prm.n_stiff * tau_ex) {
+          implicit = true;
+          tau_p = tau_im;
+        }
+      }
+    }
+    plan = true;
+  }
+
+  __device__ __forceinline__ void absorb(const SimParams& prm) {
+    const double rem = prm.t_end - t;
+#pragma unroll
+    for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * rem;
+    t = prm.t_end;
+  }
+
+  // One SSA step (Gillespie 1977 direct method) with exact G.
+  __device__ __forceinline__ void ssa_step(const SimParams& prm, const Key& key) {
+    const Words4 w = draw_block(key, pid, e, SITE_SSA, 0);
+    e = e + 1;
+    n_ssa += 1;
+    R u1, u2;
+    P::uniforms(w, &u1, &u2);
+    const double tau_s = (double)(-P::ulog(u1) / a0);
+    const double rem = prm.t_end - t;
+    if (tau_s >= rem) {
+      absorb(prm);
+      return;
+    }
+    const R thr_ = u2 * a0;
+    R cum = (R)0;
+    int jf = -1, jlast = -1;
+    bool found = false;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      if (!found) {
+        if (a[j] > (R)0) jlast = j;
+        cum = cum + a[j];
+        if (cum > thr_) {
+          jf = j;
+          found = true;
+        }
+      }
+    }
+    if (!found) jf = jlast;
+#pragma unroll
+    for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * tau_s;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      if (j == jf) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+          if (lxnet::NU[j][i] != 0) x[i] = x[i] + lxnet::NU[j][i];
+        r[j] = r[j] + 1;
+      }
+    }
+    t = t + tau_s;
+    gvalid = false;
+  }
+
+  // Dense LU with partial pivoting (first maximal pivot), in registers.
+  __device__ __forceinline__ static bool lu_solve(double (&A)[N][N], double (&b)[N]) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      int piv = c;
+      double best = __builtin_fabs(A[c][c]);
+#pragma unroll
+      for (int rr = c + 1; rr < N; ++rr) {
+        const double v = __builtin_fabs(A[rr][c]);
+        if (v > best) {
+          best = v;
+          piv = rr;
+        }
+      }
+      if (!(best > 0.0)) return false;
+#pragma unroll
+      for (int rr = c + 1; rr < N; ++rr) {
+        if (rr == piv) {
+#pragma unroll
+          for (int q = 0; q < N; ++q) {
+            const double tmp = A[c][q];
+            A[c][q] = A[rr][q];
+            A[rr][q] = tmp;
+          }
+          const double tb = b[c];
+          b[c] = b[rr];
+          b[rr] = tb;
+        }
+      }
+#pragma unroll
+      for (int rr = c + 1; rr < N; ++rr) {
+        const double l = A[rr][c] / A[c][c];
+#pragma unroll
+        for (int q = c; q < N; ++q) A[rr][q] = A[rr][q] - l * A[c][q];
+        b[rr] = b[rr] - l * b[c];
+      }
+    }
+#pragma unroll
+    for (int rr = N - 1; rr >= 0; --rr) {
+      double s = b[rr];
+#pragma unroll
+      for (int q = rr + 1; q < N; ++q) s = s - A[rr][q] * b[q];
+      b[rr] = s / A[rr][rr];
+    }
+    return true;
+  }
+
+  // Implicit leap (Rathinam et al. 2003): Newton on
+  //   F(y) = y - c - tau sum_{j noncritical} nu_j a_j(y),
+  //   c = x + sum_j nu_j (P_j - tau a_j(x)) + nu_jc [fired],
+  // with the analytic Jacobian I - tau sum_j nu_j grad a_j(y)^T.  On entry k
+  // holds the Poisson draws P_j, on success the rounded counts.
+  __device__ __forceinline__ bool implicit_counts(double tau, long long (&k)[M], int jc,
+                                                  const SimParams& prm) {
+    double ax[M], c[N], y[N];
+#pragma unroll
+    for (int j = 0; j < M; ++j) ax[j] = th[j] * g[j];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double ci = (double)x[i];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        if (lxnet::NU[j][i] == 0) continue;
+        if ((ncr >> j) & 1u) {
+          const double d = (double)k[j] - tau * ax[j];
+          ci = ci + (double)lxnet::NU[j][i] * d;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < M; ++j)
+        if (lxnet::NU[j][i] != 0 && j == jc) ci = ci + (double)lxnet::NU[j][i];
+      c[i] = ci;
+      y[i] = (double)x[i];
+    }
+    bool converged = false;
+    for (int it = 0; it < prm.newton_maxit; ++it) {
+      n_nit += 1;
+      double ay[M], gy[M];
+      g_all(y, gy);
+#pragma unroll
+      for (int j = 0; j < M; ++j) ay[j] = ((ncr >> j) & 1u) ? th[j] * gy[j] : 0.0;
+      double A[N][N], b[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+          if (lxnet::NU[j][i] != 0 && ((ncr >> j) & 1u)) s = s + (double)lxnet::NU[j][i] * ay[j];
+        b[i] = -((y[i] - c[i]) - tau * s);
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int kk = 0; kk < N; ++kk) {
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            if (lxnet::NU[j][i] == 0 || lxnet::RO[j][kk] == 0) continue;
+            if ((ncr >> j) & 1u) s = s + (double)lxnet::NU[j][i] * (th[j] * dg_of(j, kk, y));
+          }
+          A[i][kk] = (i == kk ? 1.0 : 0.0) - tau * s;
+        }
+      }
+      if (!lu_solve(A, b)) break;
+      double dmax = 0.0, ymax = 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        y[i] = y[i] + b[i];
+        const double ad = __builtin_fabs(b[i]);
+        const double ay_ = __builtin_fabs(y[i]);
+        dmax = dmax < ad ? ad : dmax;
+        ymax = ymax < ay_ ? ay_ : ymax;
+      }
+      if (!(dmax == dmax)) break;
+      if (dmax <= prm.newton_tol * (ymax < 1.0 ? 1.0 : ymax)) {
+        converged = true;
+        break;
+      }
+    }
+    if (!converged) {
+      n_nfail += 1;
+      return false;
+    }
+    double gy[M];
+    g_all(y, gy);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      if (!((ncr >> j) & 1u)) {
+        k[j] = 0;
+        continue;
+      }
+      const double v = (tau * (th[j] * gy[j]) - tau * ax[j]) + (double)k[j];
+      double kr = __builtin_round(v);
+      if (kr < 0.0) {
+        kr = 0.0;
+        n_clip += 1;
+      }
+      if (kr > 1073741824.0) kr = 1073741824.0;
+      k[j] = (long long)kr;
+    }
+    return true;
+  }
+
+  // One leap attempt with the current plan.  Returns false on rejection.
+  __device__ __forceinline__ void leap_attempt(const SimParams& prm, const Key& key) {
+    const u32 ea = e;
+    e = e + 1;
+    R tau_pp = P::inf();
+    int jc = -1;
+    R uc1 = (R)0, uc2 = (R)0;
+    if (a0c > (R)0) {
+      const Words4 w = draw_block(key, pid, ea, SITE_CRIT, 0);
+      P::uniforms(w, &uc1, &uc2);
+      tau_pp = -P::ulog(uc1) / a0c;
+    }
+    R tau_r;
+    if (tau_p < tau_pp) {
+      tau_r = tau_p;
+    } else {
+      tau_r = tau_pp;
+      const R thr_ = uc2 * a0c;
+      R cum = (R)0;
+      int jlast = -1;
+      bool found = false;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        if (!found && ((crit >> j) & 1u)) {
+          jlast = j;
+          cum = cum + a[j];
+          if (cum > thr_) {
+            jc = j;
+            found = true;
+          }
+        }
+      }
+      if (!found) jc = jlast;
+    }
+    double tau = (double)tau_r;
+    const double rem = prm.t_end - t;
+    bool last = false;
+    if (tau >= rem) {
+      tau = rem;
+      jc = -1;
+      last = true;
+    }
+    const R tau_rr = (R)tau;
+    const R lam_thr = (R)prm.lam_thr;
+    long long k[M];
+    bool overflow = false;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      k[j] = 0;
+      if ((ncr >> j) & 1u) {
+        const long long kj = poisson_sample<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
+        overflow = overflow || kj < 0;
+        k[j] = kj;
+      }
+    }
+    if (overflow) {
+      status = LANE_LAMBDA_OVERFLOW;
+      return;
+    }
+    bool ok = true;
+    if (implicit) ok = implicit_counts(tau, k, jc, prm);
+    long long xn[N];
+    if (ok) {
+#pragma unroll
+      for (int j = 0; j < M; ++j)
+        if (j == jc) k[j] = 1;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        long long v = x[i];
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+          if (lxnet::NU[j][i] != 0) v = v + (long long)lxnet::NU[j][i] * k[j];
+        xn[i] = v;
+        ok = ok && v >= 0;
+      }
+    }
+    if (!ok) {
+      n_rej += 1;
+      tau_p = tau_p / (R)2;
+      return;
+    }
+    bool big = false;
+#pragma unroll
+    for (int i = 0; i < N; ++i) big = big || xn[i] > 2147483647LL;
+#pragma unroll
+    for (int j = 0; j < M; ++j) big = big || (long long)r[j] + k[j] > 2147483647LL;
+    if (big) {
+      status = LANE_COUNT_OVERFLOW;
+      return;
+    }
+    double xd[N], gn[M];
+#pragma unroll
+    for (int i = 0; i < N; ++i) xd[i] = (double)xn[i];
+    g_all(xd, gn);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      G[j] = G[j] + (tau * (g[j] + gn[j])) * 0.5;
+      r[j] = r[j] + (int)k[j];
+      g[j] = gn[j];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = (int)xn[i];
+    t = last ? prm.t_end : t + tau;
+    if (implicit) n_im += 1;
+    else n_ex += 1;
+    plan = false;
+    gvalid = true;
+  }
+
+  // One action: an SSA step, a leap attempt, the start of an SSA burst or
+  // absorption.  Equivalent to the nested loops of the method (leap retries
+  // with halved tau', SSA bursts of n_ssa steps) flattened so that every lane
+  // makes progress on every iteration.
+  __device__ __forceinline__ void step(const SimParams& prm, const Key& key) {
+    if (!plan) propensities();
+    if (a0 == (R)0) {
+      absorb(prm);
+      return;
+    }
+    if (prm.mode == MODE_SSA || ssa_left > 0) {
+      if ((long long)e >= prm.max_steps) {
+        status = LANE_STEP_BUDGET;
+        return;
+      }
+      ssa_step(prm, key);
+      if (ssa_left > 0) ssa_left -= 1;
+      plan = false;
+      return;
+    }
+    if (!plan) make_plan(prm);
+    if (tau_p < (R)prm.k_ssa / a0 || a0c >= a0 / (R)prm.k_crit) {
+      ssa_left = implicit ? prm.n_ssa_im : prm.n_ssa_ex;
+      return;
+    }
+    if ((long long)e >= prm.max_steps) {
+      status = LANE_STEP_BUDGET;
+      return;
+    }
+    leap_attempt(prm, key);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+#ifndef LX_POLICY
+#define LX_POLICY lx::F64
+#endif
+#ifndef LX_BLOCK
+#define LX_BLOCK 64
+#endif
+
+}  // namespace lx
+
+// Plain form: lane = particle for life.
+extern "C" __global__ void __launch_bounds__(LX_BLOCK)
+    lx_sim_plain(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
+                 int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= prm.P) return;
+  const lx::Key key{prm.k0, prm.k1};
+  lx::Lane<LX_POLICY> lane;
+  lane.load(p, theta, x0, r_out, G_out, prm);
+  while (lane.active(prm)) lane.step(prm, key);
+  lane.store(p, x_out, r_out, G_out, stats);
+}
+
+#ifdef LX_HOOKS
+// Step decision on fixed states (test hook).
+extern "C" __global__ void __launch_bounds__(64)
+    lx_hook_tau(const double* __restrict__ theta, const int* __restrict__ xs, double* a_out,
+                unsigned int* crit_out, unsigned int* eq_out, double* tau_out, int* action,
+                lx::SimParams prm) {
+  typedef LX_POLICY::R R;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= prm.P) return;
+  lx::Lane<LX_POLICY> lane;
+  lx::SimParams p2 = prm;
+  p2.accumulate = 0;
+  p2.pid_base = 0;
+  lane.load(q, theta, xs, nullptr, nullptr, p2);
+  lane.propensities();
+  R tau_ex, tau_im;
+  unsigned int eq;
+  lane.decide(prm, &tau_ex, &tau_im, &eq);
+  for (int j = 0; j < lx::M; ++j) a_out[q * lx::M + j] = (double)lane.a[j];
+  crit_out[q] = lane.crit;
+  eq_out[q] = eq;
+  tau_out[2 * q] = (double)tau_ex;
+  tau_out[2 * q + 1] = (double)tau_im;
+  int act;
+  if (lane.a0 == (R)0) act = 3;
+  else if (lane.tau_p < (R)prm.k_ssa / lane.a0 || lane.a0c >= lane.a0 / (R)prm.k_crit) act = 2;
+  else act = lane.implicit ? 1 : 0;
+  action[q] = act;
+}
+
+// Implicit-leap solve on fixed inputs (test hook); binary64 policy.
+extern "C" __global__ void __launch_bounds__(64)
+    lx_hook_implicit(const double* __restrict__ theta, const int* __restrict__ xs,
+                     const double* __restrict__ tau, const long long* __restrict__ Pj,
+                     const int* __restrict__ jc, long long* k_out, int* ok_out, int* it_out,
+                     lx::SimParams prm) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= prm.P) return;
+  lx::Lane<lx::F64> lane;
+  lx::SimParams p2 = prm;
+  p2.accumulate = 0;
+  p2.pid_base = 0;
+  lane.load(q, theta, xs, nullptr, nullptr, p2);
+  lane.propensities();
+  lane.ncr = 0;
+  for (int j = 0; j < lx::M; ++j)
+    if (lane.a[j] > 0.0 && j != jc[q]) lane.ncr |= 1u << j;
+  long long k[lx::M];
+  for (int j = 0; j < lx::M; ++j) k[j] = Pj[q * lx::M + j];
+  const bool ok = lane.implicit_counts(tau[q], k, jc[q], prm);
+  for (int j = 0; j < lx::M; ++j) k_out[q * lx::M + j] = ok ? k[j] : 0;
+  ok_out[q] = ok ? 1 : 0;
+  it_out[q] = (int)lane.n_nit;
+}
+#endif

@@ -1,0 +1,157 @@
+"""Bit-exact parity of the production device functions with the oracle.
+
+The hooks run the kernels' own Philox, uniform maps, exp/log, log-factorial,
+Poisson and exponential samplers, the network-specialised step decision
+(propensities, critical set, tau_ex / tau_im, partial equilibrium, action)
+and the implicit Newton solve on fixed inputs; the oracle computes the same
+quantities on the CPU.  Floating point decides integers here (Poisson counts,
+critical sets, actions), so both sides must agree exactly.
+"""
+
+import numpy as np
+import pytest
+
+from paper_1608_07058_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SEED = 160807058
+
+
+@pytest.fixture(scope="module")
+def lxm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_07058_amd import lx
+    lx.lib()
+    return lx
+
+
+def test_philox_bit_exact(lxm, orc):
+    rng = np.random.default_rng(11)
+    ctr = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, size=(4096, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[:5] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4, [1, 0, 0, 0], [0, 0, 0, 1], [7, 8, 9, 10]]
+    key[:2] = [[0, 0], [0xFFFFFFFF, 0xFFFFFFFF]]
+    assert np.array_equal(lxm.test_philox(ctr, key), orc.philox(ctr, key))
+
+
+def test_uniform_maps_bit_exact(lxm, orc):
+    rng = np.random.default_rng(12)
+    w = rng.integers(0, 2**32, size=(8192, 2), dtype=np.uint64).astype(np.uint32)
+    w[0] = [0, 0]
+    w[1] = [0xFFFFFFFF, 0xFFFFFFFF]
+    assert np.array_equal(lxm.test_uniform_f64(w), orc.uniform_f64(w))
+    assert np.array_equal(lxm.test_uniform_f32(w[:, 0]), orc.uniform_f32(w[:, 0]))
+
+
+def test_math_bit_exact(lxm, orc):
+    rng = np.random.default_rng(13)
+    x = np.concatenate([rng.uniform(-40, 0, 20000), rng.uniform(-700, 700, 2000)])
+    assert np.array_equal(lxm.test_math("exp_f64", x), orc.exp_f64(x))
+    y = np.concatenate([rng.uniform(0, 1, 20000), 10.0 ** rng.uniform(-300, 300, 2000),
+                        [2.0**-53, 1 - 2.0**-53, 1e-310]])
+    assert np.array_equal(lxm.test_math("log_f64", y), orc.log_f64(y))
+    xf = np.concatenate([rng.uniform(-30, 0, 20000), rng.uniform(-87, 88, 2000)]).astype(np.float32)
+    assert np.array_equal(lxm.test_math("exp_f32", xf), orc.exp_f32(xf))
+    yf = np.concatenate([rng.uniform(0, 1, 20000), 10.0 ** rng.uniform(-37, 37, 2000)]).astype(np.float32)
+    assert np.array_equal(lxm.test_math("log_f32", yf), orc.log_f32(yf))
+    k = np.concatenate([np.arange(0, 300), np.round(10 ** rng.uniform(2, 9, 2000))]).astype(np.float64)
+    assert np.array_equal(lxm.test_math("lfact", k), orc.lfact(k))
+
+
+def test_sqrt_is_correctly_rounded(lxm):
+    # PTRS needs sqrt; both sides rely on the IEEE correctly rounded operation.
+    rng = np.random.default_rng(14)
+    x = np.concatenate([10.0 ** rng.uniform(-10, 12, 50000), rng.uniform(10, 1e7, 50000)])
+    assert np.array_equal(lxm.test_math("sqrt_f64", x), np.sqrt(x))
+    xf = x.astype(np.float32)
+    assert np.array_equal(lxm.test_math("sqrt_f32", xf), np.sqrt(xf))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_poisson_bit_exact(lxm, orc, precision):
+    rng = np.random.default_rng(15)
+    lam = np.concatenate([
+        rng.uniform(0, 10, 20000), [0.0, 1e-9, 9.999999, 10.0, 10.000001],
+        10 ** rng.uniform(1, 4, 20000), 10 ** rng.uniform(4, 6.5, 5000),
+    ])
+    n = lam.shape[0]
+    pid = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+    e = rng.integers(0, 10**6, size=n).astype(np.uint32)
+    site = rng.integers(0, 32, size=n).astype(np.uint32)
+    got = lxm.test_poisson(lam, pid, e, site, precision=precision)
+    ref = orc.poisson(lam, pid, e, site, precision=precision)
+    assert np.array_equal(got, ref)
+    # a different stream and threshold too
+    got = lxm.test_poisson(lam[:5000], pid[:5000], e[:5000], site[:5000], stream_id=3,
+                           lambda_thr=20.0, precision=precision)
+    ref = orc.poisson(lam[:5000], pid[:5000], e[:5000], site[:5000], stream=3, lambda_thr=20.0,
+                      precision=precision)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_exponential_bit_exact(lxm, orc, precision):
+    pid = np.arange(50000, dtype=np.uint32)
+    got = lxm.test_exponential(pid, 17, precision=precision)
+    ref = orc.exponential(pid, 17, precision=precision)
+    assert np.array_equal(got, ref)
+
+
+NETS = {
+    "birth_death": W.birth_death(),
+    "dimer": W.dimer(),
+    "dimer_stiff": W.dimer_stiff(),
+    "isomerisation": W.isomerisation(),
+    "schlogl": W.schlogl(),
+    "telegraph": W.telegraph(),
+}
+
+
+def _random_states(net, n, rng):
+    scale = np.maximum(net.x0, 50)
+    x = rng.integers(0, 3 * scale + 1, size=(n, net.N))
+    x[: n // 4] = rng.integers(0, 12, size=(n // 4, net.N))  # near-critical states
+    x[0] = 0
+    th = net.theta * rng.gamma(2.0, 0.5, size=(n, net.M))
+    return x.astype(np.int32), th
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("mode", ["adaptive", "explicit"])
+@pytest.mark.parametrize("name", sorted(NETS))
+def test_step_decision_bit_exact(lxm, orc, name, mode, precision):
+    net = NETS[name]
+    rng = np.random.default_rng(sum(map(ord, name)))
+    x, th = _random_states(net, 3000, rng)
+    h = lxm.Network(net.m, net.p)
+    got = lxm.test_tau_select(h, th, x, 0.03, mode, precision=precision)
+    ref = orc.tau_select(net.m, net.p, th, x, mode=mode, precision=precision)
+    assert np.array_equal(got["a"], ref["a"])
+    assert np.array_equal(got["crit"], ref["crit"])
+    assert np.array_equal(got["eq"], ref["eq"])
+    assert np.array_equal(got["tau_ex"], ref["tau_ex"])
+    assert np.array_equal(got["tau_im"], ref["tau_im"])
+    assert np.array_equal(got["action"], ref["action"])
+
+
+@pytest.mark.parametrize("name", ["dimer", "dimer_stiff", "isomerisation", "schlogl"])
+def test_implicit_solve_bit_exact(lxm, orc, name):
+    net = NETS[name]
+    rng = np.random.default_rng(21)
+    Q = 1000
+    x, th = _random_states(net, Q, rng)
+    x = np.maximum(x, 1)
+    tau = rng.uniform(1e-4, 0.5, Q)
+    res = orc.tau_select(net.m, net.p, th, x)
+    Pj = rng.poisson(np.minimum(res["a"] * tau[:, None], 1e6))
+    jc = np.where(rng.uniform(size=Q) < 0.3, rng.integers(0, net.M, Q), -1).astype(np.int32)
+    h = lxm.Network(net.m, net.p)
+    got = lxm.test_implicit(h, th, x, tau, Pj, jc)
+    ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc)
+    assert np.array_equal(got["ok"], ref["ok"])
+    assert np.array_equal(got["iters"], ref["iters"])
+    assert np.array_equal(got["k"], ref["k"])
+    assert got["ok"].mean() > 0.5
