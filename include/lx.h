@@ -59,8 +59,13 @@ typedef int32_t lx_status;
 
 /* Schedules. */
 #define LX_SCHED_PLAIN 0   /* one lane per particle for its whole life */
-#define LX_SCHED_BATCHED 1 /* persistent blocks, work-stealing refill of finished
-                              lanes and regrouping of lanes by action */
+#define LX_SCHED_BATCHED 1 /* persistent blocks; each block owns a contiguous range of
+                              particles and refills finished lanes from it (work
+                              stealing through an LDS cursor); lanes in SSA bursts
+                              take several SSA steps per leap iteration of the
+                              other lanes (divergence balancing); waves may run
+                              with 16 or 32 active lanes when the ensemble is too
+                              small to give every SIMD a full wave */
 
 /* Per-trajectory status codes (lx_stats.status). */
 #define LX_LANE_OK 0
@@ -94,9 +99,9 @@ typedef struct lx_options {
   int32_t newton_maxit; /* default 20 */
   int32_t block_size;   /* threads per block (64..256, multiple of 64); 0 = default 64 */
   int64_t max_steps;    /* attempt budget per trajectory      default 10^7 (< 2^32) */
-  int32_t chunk;        /* batched: particles per cursor grab, 0 = default */
-  int32_t regroup;      /* batched: loop iterations between regroups, 0 = default */
-  int32_t blocks_per_cu;/* batched: resident blocks per CU, 0 = default */
+  int32_t lanes_per_wave; /* batched: active lanes per wave, 16/32/64; 0 = chosen from P */
+  int32_t ssa_k;        /* batched: SSA steps per leap iteration, 1..64; 0 = default 4 */
+  int32_t blocks_per_cu;/* batched: resident blocks per CU, 1..8; 0 = default 2 */
   int32_t reserved[7];
 } lx_options;
 

@@ -283,6 +283,12 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
     return fail(LX_E_INVALID, "option out of range");
   if (o.block_size != 0 && (o.block_size < 64 || o.block_size > MAX_BLOCK || o.block_size % 64 != 0))
     return fail(LX_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
+  if (o.lanes_per_wave != 0 && o.lanes_per_wave != 16 && o.lanes_per_wave != 32 &&
+      o.lanes_per_wave != 64)
+    return fail(LX_E_INVALID, "lanes_per_wave must be 0, 16, 32 or 64");
+  if (o.ssa_k < 0 || o.ssa_k > 64) return fail(LX_E_INVALID, "ssa_k must be in [0, 64]");
+  if (o.blocks_per_cu < 0 || o.blocks_per_cu > 8)
+    return fail(LX_E_INVALID, "blocks_per_cu must be in [0, 8]");
   if ((uint64_t)o.pid_base + (uint64_t)P > 4294967296ull)
     return fail(LX_E_INVALID, "pid_base + P exceeds 2^32 particle ids");
   memset(prm, 0, sizeof(*prm));
@@ -420,7 +426,7 @@ lx_status lx_network_prepare(lx_network net, int32_t precision, int32_t schedule
     return fail(LX_E_INVALID, "schedule must be LX_SCHED_*");
   if (block_size != 0 && (block_size < 64 || block_size > MAX_BLOCK || block_size % 64 != 0))
     return fail(LX_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
-  const int block = block_size ? block_size : 64;
+  const int block = block_size ? block_size : (schedule == LX_SCHED_BATCHED ? 256 : 64);
   std::vector<char> code;
   return compile_source(
       kernel_source(*net, schedule == LX_SCHED_BATCHED ? "batched" : "plain", precision, block),
@@ -456,18 +462,42 @@ lx_status lx_simulate(lx_network net, int64_t P, const double* theta, const int3
   if (!theta || !x0 || !x_out || !r_out || !G_out)
     return fail(LX_E_INVALID, "null input/output pointer");
   hipStream_t s = (hipStream_t)stream;
-  const int block = o.block_size ? o.block_size : 64;
+  const bool batched = o.schedule == LX_SCHED_BATCHED;
+  const int block = o.block_size ? o.block_size : (batched ? 256 : 64);
   hipFunction_t fn;
-  st = get_kernel(net, "plain", o.precision, block, "lx_sim_plain", &fn);
+  st = get_kernel(net, batched ? "batched" : "plain", o.precision, block,
+                  batched ? "lx_sim_batched" : "lx_sim_plain", &fn);
   if (st != LX_OK) return st;
-  const long long grid = (P + block - 1) / block;
+  long long grid = (P + block - 1) / block;
+  if (batched) {
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device attributes");
+    // Active lanes per wave: full waves when the ensemble gives every SIMD
+    // (4 per CU) a wave, otherwise 32 or 16 so that more SIMDs are busy and
+    // each wave carries fewer divergent paths.
+    int lanes = o.lanes_per_wave;
+    if (lanes == 0) {
+      const long long simds = 4LL * cus;
+      lanes = P >= 64 * simds ? 64 : (P >= 32 * simds ? 32 : 16);
+    }
+    const long long round = (long long)(block / 64) * lanes;
+    const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
+    long long per_block = (P + max_grid - 1) / max_grid;
+    if (per_block < round) per_block = round;
+    prm.per_block = per_block;
+    prm.lanes = lanes;
+    prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
+    grid = (P + per_block - 1) / per_block;
+  }
   if (grid > 0x7fffffffLL) return fail(LX_E_INVALID, "P too large for one launch");
   lx::Stats* sp = (lx::Stats*)stats;
   void* args[] = {(void*)&theta, (void*)&x0, (void*)&x_out, (void*)&r_out,
                   (void*)&G_out, (void*)&sp, (void*)&prm};
   hipError_t e = hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0, s,
                                        args, nullptr);
-  if (e != hipSuccess) return hip_fail(e, "launch lx_sim_plain");
+  if (e != hipSuccess) return hip_fail(e, batched ? "launch lx_sim_batched" : "launch lx_sim_plain");
   return LX_OK;
 }
 

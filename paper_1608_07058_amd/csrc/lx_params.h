@@ -24,9 +24,9 @@ struct SimParams {
   unsigned int k0, k1, pid_base;
   int n_c, n_ssa_ex, n_ssa_im, newton_maxit, kcap, mode, accumulate;
   // batched scheduler
-  unsigned int* cursor;   // global particle cursor (work stealing), or null
-  int chunk;              // particles taken per cursor increment
-  int regroup;            // regroup interval in loop iterations (0: never)
+  long long per_block;    // particles owned by each block (contiguous range)
+  int lanes;              // active lanes per wave (16, 32 or 64)
+  int ssa_k;              // SSA steps a lane in an SSA burst takes per leap iteration
 };
 
 // Per-trajectory statistics (layout of the public lx_stats).

@@ -566,36 +566,54 @@ struct Lane {
     gvalid = true;
   }
 
-  // One action: an SSA step, a leap attempt, the start of an SSA burst or
-  // absorption.  Equivalent to the nested loops of the method (leap retries
-  // with halved tau', SSA bursts of n_ssa steps) flattened so that every lane
-  // makes progress on every iteration.
+  // One action: an SSA step, a leap attempt, or absorption.  Equivalent to
+  // the nested loops of the method (leap retries with halved tau', SSA bursts
+  // of n_ssa steps) flattened so that every lane makes progress on every
+  // iteration; a burst decided here starts with its first SSA step at once.
   __device__ __forceinline__ void step(const SimParams& prm, const Key& key) {
     if (!plan) propensities();
     if (a0 == (R)0) {
       absorb(prm);
       return;
     }
+    if (prm.mode != MODE_SSA && ssa_left == 0) {
+      if (!plan) make_plan(prm);
+      if (tau_p < (R)prm.k_ssa / a0 || a0c >= a0 / (R)prm.k_crit)
+        ssa_left = implicit ? prm.n_ssa_im : prm.n_ssa_ex;
+    }
+    if ((long long)e >= prm.max_steps) {
+      status = LANE_STEP_BUDGET;
+      return;
+    }
     if (prm.mode == MODE_SSA || ssa_left > 0) {
-      if ((long long)e >= prm.max_steps) {
-        status = LANE_STEP_BUDGET;
-        return;
-      }
       ssa_step(prm, key);
       if (ssa_left > 0) ssa_left -= 1;
       plan = false;
       return;
     }
-    if (!plan) make_plan(prm);
-    if (tau_p < (R)prm.k_ssa / a0 || a0c >= a0 / (R)prm.k_crit) {
-      ssa_left = implicit ? prm.n_ssa_im : prm.n_ssa_ex;
+    leap_attempt(prm, key);
+  }
+
+  // True when the next action is an SSA step (a burst in progress, or SSA
+  // mode); such a lane needs no plan.
+  __device__ __forceinline__ bool in_ssa(const SimParams& prm) const {
+    return prm.mode == MODE_SSA || ssa_left > 0;
+  }
+
+  // An SSA step of a lane in a burst (the SSA branch of step()).
+  __device__ __forceinline__ void ssa_only(const SimParams& prm, const Key& key) {
+    propensities();
+    if (a0 == (R)0) {
+      absorb(prm);
       return;
     }
     if ((long long)e >= prm.max_steps) {
       status = LANE_STEP_BUDGET;
       return;
     }
-    leap_attempt(prm, key);
+    ssa_step(prm, key);
+    if (ssa_left > 0) ssa_left -= 1;
+    plan = false;
   }
 };
 
@@ -611,7 +629,7 @@ struct Lane {
 
 }  // namespace lx
 
-// Plain form: lane = particle for life.
+// Plain form: lane = particle for life, 64 lanes per wave.
 extern "C" __global__ void __launch_bounds__(LX_BLOCK)
     lx_sim_plain(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
                  int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
@@ -623,6 +641,50 @@ extern "C" __global__ void __launch_bounds__(LX_BLOCK)
   while (lane.active(prm)) lane.step(prm, key);
   lane.store(p, x_out, r_out, G_out, stats);
 }
+
+#ifdef LX_BATCHED
+// Batched form.  Block b owns particles [b*per_block, (b+1)*per_block); its
+// waves run `lanes` active lanes each and refill a finished lane with the
+// block's next particle through an LDS cursor (work stealing within the
+// block), until the range is exhausted.  Every iteration, lanes in an SSA
+// burst take up to ssa_k SSA steps while the other lanes plan and take one
+// leap attempt, which balances the divergent paths (an SSA step costs a
+// fraction of a leap).  Per trajectory the sequence of actions, and hence
+// every result, is the one of the plain form.
+extern "C" __global__ void __launch_bounds__(LX_BLOCK)
+    lx_sim_batched(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
+                   int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
+  __shared__ unsigned long long next;
+  const int lane_id = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const long long lo = (long long)blockIdx.x * prm.per_block;
+  long long hi = lo + prm.per_block;
+  if (hi > prm.P) hi = prm.P;
+  if (threadIdx.x == 0) next = (unsigned long long)(lo + (long long)waves * prm.lanes);
+  __syncthreads();
+  const lx::Key key{prm.k0, prm.k1};
+  long long p = lo + (long long)wave * prm.lanes + lane_id;
+  bool has = lane_id < prm.lanes && p < hi;
+  lx::Lane<LX_POLICY> lane;
+  if (has) lane.load(p, theta, x0, r_out, G_out, prm);
+  while (has) {
+    if (lane.active(prm)) {
+      for (int k = 0; k < prm.ssa_k; ++k) {
+        if (!(lane.active(prm) && lane.in_ssa(prm))) break;
+        lane.ssa_only(prm, key);
+      }
+      if (lane.active(prm) && !lane.in_ssa(prm)) lane.step(prm, key);
+    }
+    if (!lane.active(prm)) {
+      lane.store(p, x_out, r_out, G_out, stats);
+      p = (long long)atomicAdd(&next, 1ull);
+      has = p < hi;
+      if (has) lane.load(p, theta, x0, r_out, G_out, prm);
+    }
+  }
+}
+#endif
 
 #ifdef LX_HOOKS
 // Step decision on fixed states (test hook).

@@ -86,25 +86,48 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("schedule", ["plain", "batched"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision):
+def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision, schedule):
     name, net, mode, t_end, P = case
     theta = W.gamma_prior_theta(net, P, seed=7)
     _, x0 = W.tile(net, P)
-    got = gpu_run(lxm, net, theta, x0, t_end, mode, precision=precision)
+    got = gpu_run(lxm, net, theta, x0, t_end, mode, precision=precision, schedule=schedule)
     ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode=mode, precision=precision)
-    assert_same(got, ref, f"{name}/{precision}")
+    assert_same(got, ref, f"{name}/{precision}/{schedule}")
     assert np.all(got["stats"]["status"] == 0)
 
 
+@pytest.mark.parametrize("knobs", [
+    dict(lanes_per_wave=16, ssa_k=1, blocks_per_cu=1),
+    dict(lanes_per_wave=32, ssa_k=4, blocks_per_cu=1, block_size=64),
+    dict(lanes_per_wave=64, ssa_k=16, blocks_per_cu=1, block_size=128),
+    dict(lanes_per_wave=64, ssa_k=64, blocks_per_cu=8),
+])
+def test_batched_refill_and_knobs(lxm, orc, knobs):
+    # Few resident blocks force every lane to refill from its block's range
+    # many times; no knob may change any result.
+    net = W.telegraph()
+    P = 40000
+    theta = W.gamma_prior_theta(net, P, seed=11)
+    _, x0 = W.tile(net, P)
+    got = gpu_run(lxm, net, theta, x0, 20.0, "adaptive", precision="mixed", schedule="batched",
+                  **knobs)
+    ref = orc.simulate(net.m, net.p, theta, x0, 20.0, mode="adaptive", precision="mixed")
+    assert_same(got, ref, str(knobs))
+
+
+@pytest.mark.parametrize("schedule", ["plain", "batched"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_full_size_dimer_sampled(lxm, orc, precision):
-    # The benchmark workload (16384 trajectories, 64-thread blocks), checked on
-    # trajectories sampled across the grid and recomputed by the oracle.
+def test_full_size_dimer_sampled(lxm, orc, precision, schedule):
+    # The benchmark workload (16384 trajectories, in the launch configuration
+    # the benchmark times), checked on trajectories sampled across the grid and
+    # recomputed by the oracle.
     wl = W.dimer_workload()
     net, theta, x0 = wl.nets[0], wl.theta[0], wl.x0[0]
-    got = gpu_run(lxm, net, theta, x0, wl.t_end, wl.mode, precision=precision)
+    got = gpu_run(lxm, net, theta, x0, wl.t_end, wl.mode, precision=precision,
+                  schedule=schedule)
     rng = np.random.default_rng(5)
     sample = np.concatenate([[0, 63, 64, wl.P - 1], rng.choice(wl.P, 60, replace=False)])
     for p in sample:
@@ -218,6 +241,10 @@ def test_invalid_arguments_raise(lxm):
         lxm.simulate(h, th, xi, 1.0, lambda_thr=100.0)
     with pytest.raises(lxm.LxError):
         lxm.simulate(h, th, xi, 1.0, block_size=100)
+    with pytest.raises(lxm.LxError):
+        lxm.simulate(h, th, xi, 1.0, schedule="batched", lanes_per_wave=8)
+    with pytest.raises(lxm.LxError):
+        lxm.simulate(h, th, xi, 1.0, schedule="batched", ssa_k=100)
 
 
 # ---------------------------------------------------------------------------
@@ -295,6 +322,7 @@ def test_distribution_dimer(lxm, orc, precision):
     net = W.dimer()
     P = 100000
     theta, x0 = W.tile(net, P)
-    got = gpu_run(lxm, net, theta, x0, 30.0, "adaptive", precision=precision, seed=3)
+    got = gpu_run(lxm, net, theta, x0, 30.0, "adaptive", precision=precision, seed=3,
+                  schedule="batched")
     ref = orc.simulate(net.m, net.p, theta, x0, 30.0, mode="adaptive", seed=4)
     _compare_distributions(got, ref, f"dimer/{precision}")
