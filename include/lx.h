@@ -102,7 +102,9 @@ typedef struct lx_options {
   int32_t lanes_per_wave; /* batched: active lanes per wave, 16/32/64; 0 = chosen from P */
   int32_t ssa_k;        /* batched: SSA steps per leap iteration, 1..64; 0 = default 4 */
   int32_t blocks_per_cu;/* batched: resident blocks per CU, 1..8; 0 = default 2 */
-  int32_t reserved[7];
+  uint32_t pid_stride;  /* row p uses RNG particle id pid_base + p * pid_stride;
+                           0 means 1 (interleaved ids for sharding or mixed sets) */
+  int32_t reserved[6];
 } lx_options;
 
 /* Per-trajectory statistics (80 bytes). */
@@ -180,6 +182,31 @@ lx_status lx_simulate(lx_network net, int64_t P, const double* theta, const int3
                       double t_end, double eps, int32_t mode, const lx_options* opt,
                       int32_t* x_out, int32_t* r_out, double* G_out, lx_stats* stats,
                       void* stream);
+
+/* One network of a multi-network simulation. */
+typedef struct lx_set_item {
+  lx_network net;
+  int64_t P;
+  const double* theta; /* device [P][M of net] */
+  const int32_t* x0;   /* device [P][N of net] */
+  int32_t* x_out;      /* device [P][N] */
+  int32_t* r_out;      /* device [P][M] */
+  double* G_out;       /* device [P][M] */
+  lx_stats* stats;     /* device [P] or NULL */
+  uint32_t pid_base;   /* RNG particle id of row p: pid_base + p * pid_stride */
+  uint32_t pid_stride; /* 0 means 1 */
+} lx_set_item;
+
+/* Simulate several networks in one launch (batched schedule): K in [1, 8]
+ * items, each with its own network, ensemble and buffers; blocks are assigned
+ * to items in proportion to their sizes, each block runs one network, so no
+ * wave mixes networks.  Results are identical to K separate lx_simulate calls
+ * with the same ids.  t_end, eps, mode and options (precision, control
+ * constants, seed, rng_stream, accumulate, tuning) are shared; opt->schedule,
+ * pid_base and pid_stride are ignored in favour of the items.  Errors as for
+ * lx_simulate. */
+lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, double eps,
+                          int32_t mode, const lx_options* opt, void* stream);
 
 /* ---- Test hooks: run the production device functions on fixed inputs. ----
  * All pointers are device memory; n elements; enqueued on stream. */

@@ -489,6 +489,7 @@ typedef struct {
   int32_t n_c, n_ssa_ex, n_ssa_im, newton_maxit;
   uint32_t rng_stream, pid_base;
   int32_t accumulate, mode, precision, nthreads;
+  uint32_t pid_stride, pad;  // particle p uses id pid_base + p * pid_stride (0 means 1)
 } orc_options;
 
 typedef struct {
@@ -957,7 +958,8 @@ void run_range(const Net& net, const orc_options& o, double t_end, int64_t lo, i
   const int N = net.N, M = net.M;
   for (int64_t p = lo; p < hi; ++p) {
     Traj<P> tr(net, o, t_end);
-    tr.run(o.pid_base + (uint32_t)p, theta + p * M, x0 + p * N, xo + p * N, ro + p * M,
+    const uint32_t stride = o.pid_stride ? o.pid_stride : 1;
+    tr.run(o.pid_base + (uint32_t)p * stride, theta + p * M, x0 + p * N, xo + p * N, ro + p * M,
            Go + p * M, so ? so + p : nullptr);
   }
 }

@@ -170,7 +170,7 @@ struct lx_network_s {
 
   ~lx_network_s() {
     for (auto& kv : kernels)
-      if (kv.second.mod) hipModuleUnload(kv.second.mod);
+      if (kv.second.mod) (void)hipModuleUnload(kv.second.mod);
   }
 };
 
@@ -178,7 +178,7 @@ namespace {
 
 std::string table_src(const char* name, const std::vector<int>& v, int rows, int cols) {
   std::ostringstream s;
-  s << "constexpr int " << name << "[" << rows << "][" << cols << "] = {";
+  s << "  static constexpr int " << name << "[" << rows << "][" << cols << "] = {";
   for (int r = 0; r < rows; ++r) {
     s << (r ? ",{" : "{");
     for (int c = 0; c < cols; ++c) s << (c ? "," : "") << v[(size_t)r * cols + c];
@@ -190,24 +190,31 @@ std::string table_src(const char* name, const std::vector<int>& v, int rows, int
 
 std::string vec_src(const char* name, const std::vector<int>& v) {
   std::ostringstream s;
-  s << "constexpr int " << name << "[" << v.size() << "] = {";
+  s << "  static constexpr int " << name << "[" << v.size() << "] = {";
   for (size_t q = 0; q < v.size(); ++q) s << (q ? "," : "") << v[q];
   s << "};\n";
   return s.str();
 }
 
-// Compile-time description of the network for the kernel source.
+// Compile-time description of the network for the kernel source: a traits
+// struct named LxNet<k> (the "@" placeholder is replaced by k).
 std::string network_source(const lx_network_s& n) {
   std::ostringstream s;
-  s << "namespace lxnet {\n";
-  s << "constexpr int N = " << n.N << ";\nconstexpr int M = " << n.M << ";\n";
-  s << "constexpr int NPAIRS = " << n.npairs << ";\n";
+  s << "struct LxNet@ {\n";
+  s << "  static constexpr int N = " << n.N << ";\n  static constexpr int M = " << n.M << ";\n";
+  s << "  static constexpr int NPAIRS = " << n.npairs << ";\n";
   s << table_src("RO", n.ro, n.M, n.N);
   s << table_src("NU", n.nu, n.M, n.N);
   s << vec_src("PHI", n.phi);
   s << vec_src("PARTNER", n.partner);
-  s << "}  // namespace lxnet\n";
+  s << "};\n";
   return s.str();
+}
+
+std::string named_net(const lx_network_s& n, int k) {
+  std::string src = n.netsrc;
+  const size_t at = src.find('@');
+  return src.replace(at, 1, std::to_string(k));
 }
 
 // Full hipRTC source of one kernel variant of a network.
@@ -218,7 +225,36 @@ std::string kernel_source(const lx_network_s& net, const char* variant, int prec
   src << "#define LX_BLOCK " << block << "\n";
   if (strcmp(variant, "hooks") == 0) src << "#define LX_HOOKS 1\n";
   if (strcmp(variant, "batched") == 0) src << "#define LX_BATCHED 1\n";
-  src << lx_src_params << "\n" << lx_src_device << "\n" << net.netsrc << "\n" << lx_src_sim;
+  src << lx_src_params << "\n" << lx_src_device << "\n" << named_net(net, 0)
+      << "typedef LxNet0 LxNet;\n" << lx_src_sim;
+  return src.str();
+}
+
+// hipRTC source of the multi-network kernel: every network of the set as
+// LxNet<k>, and a kernel that picks the network of its block.
+std::string set_source(const std::vector<const lx_network_s*>& nets, int precision, int block) {
+  std::ostringstream src;
+  src << "// generated by liblx (network set)\n";
+  src << "#define LX_POLICY " << (precision == LX_PREC_MIXED ? "lx::Mixed" : "lx::F64") << "\n";
+  src << "#define LX_BLOCK " << block << "\n#define LX_SET 1\n";
+  src << lx_src_params << "\n" << lx_src_device << "\n";
+  for (size_t k = 0; k < nets.size(); ++k) src << named_net(*nets[k], (int)k);
+  src << "typedef LxNet0 LxNet;\n" << lx_src_sim << "\n";
+  src << "extern \"C\" __global__ void __launch_bounds__(LX_BLOCK)\n"
+         "    lx_sim_set(lx::SetArgs a, lx::SimParams prm) {\n"
+         "  __shared__ unsigned long long next;\n"
+         "  int k = 0;\n"
+         "  while (k + 1 < a.K && (int)blockIdx.x >= a.it[k + 1].block_begin) ++k;\n"
+         "  const lx::SetItem& it = a.it[k];\n"
+         "  lx::SimParams q = prm;\n"
+         "  q.P = it.P;\n  q.per_block = it.per_block;\n  q.lanes = it.lanes;\n"
+         "  q.pid_base = it.pid_base;\n  q.pid_stride = it.pid_stride;\n"
+         "  const long long blk = (long long)blockIdx.x - it.block_begin;\n"
+         "  switch (k) {\n";
+  for (size_t k = 0; k < nets.size(); ++k)
+    src << "    case " << k << ": lx::run_batched<LxNet" << k
+        << ">(blk, it.theta, it.x0, it.x_out, it.r_out, it.G_out, it.stats, q, &next); break;\n";
+  src << "  }\n}\n";
   return src.str();
 }
 
@@ -237,33 +273,60 @@ lx_status check_device(int* dev_out) {
 
 // Fetch (compiling on first use) a kernel of the network for the current
 // device.  variant: "plain", "batched" or "hooks"; precision LX_PREC_*.
-lx_status get_kernel(lx_network_s* net, const char* variant, int precision, int block,
-                     const char* fname, hipFunction_t* fn) {
+// Fetch (compiling and loading on first use) a kernel for the current device
+// from the cache of network `owner`; `make_src` produces its source.
+template <class F>
+lx_status get_kernel_src(lx_network_s* owner, const std::string& variant_key, F make_src,
+                         const char* fname, hipFunction_t* fn) {
   int dev = 0;
   lx_status st = check_device(&dev);
   if (st != LX_OK) return st;
   std::ostringstream key;
-  key << variant << "/" << precision << "/" << block << "/" << fname << "/dev" << dev;
-  std::lock_guard<std::mutex> lock(net->mu);
-  auto it = net->kernels.find(key.str());
-  if (it != net->kernels.end()) {
+  key << variant_key << "/" << fname << "/dev" << dev;
+  std::lock_guard<std::mutex> lock(owner->mu);
+  auto it = owner->kernels.find(key.str());
+  if (it != owner->kernels.end()) {
     *fn = it->second.fn;
     return LX_OK;
   }
   std::vector<char> code;
-  st = compile_source(kernel_source(*net, variant, precision, block), &code);
+  st = compile_source(make_src(), &code);
   if (st != LX_OK) return st;
   Kernel k;
   hipError_t e = hipModuleLoadData(&k.mod, code.data());
   if (e != hipSuccess) return hip_fail(e, "hipModuleLoadData");
   e = hipModuleGetFunction(&k.fn, k.mod, fname);
   if (e != hipSuccess) {
-    hipModuleUnload(k.mod);
+    (void)hipModuleUnload(k.mod);
     return hip_fail(e, "hipModuleGetFunction");
   }
-  net->kernels[key.str()] = k;
+  owner->kernels[key.str()] = k;
   *fn = k.fn;
   return LX_OK;
+}
+
+lx_status get_kernel(lx_network_s* net, const char* variant, int precision, int block,
+                     const char* fname, hipFunction_t* fn) {
+  std::ostringstream key;
+  key << variant << "/" << precision << "/" << block;
+  return get_kernel_src(net, key.str(),
+                        [&]() { return kernel_source(*net, variant, precision, block); }, fname, fn);
+}
+
+// Active lanes per wave of the batched schedule: full waves when the ensemble
+// gives every SIMD (4 per CU) a wave, otherwise 32 or 16, so that more SIMDs
+// are busy and each wave carries fewer divergent paths.
+int choose_lanes(int requested, long long P, int cus) {
+  if (requested) return requested;
+  const long long simds = 4LL * cus;
+  return P >= 64 * simds ? 64 : (P >= 32 * simds ? 32 : 16);
+}
+
+lx_status device_cus(int* cus) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return e == hipSuccess ? LX_OK : hip_fail(e, "device attributes");
 }
 
 lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, int32_t mode,
@@ -289,8 +352,11 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
   if (o.ssa_k < 0 || o.ssa_k > 64) return fail(LX_E_INVALID, "ssa_k must be in [0, 64]");
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 8)
     return fail(LX_E_INVALID, "blocks_per_cu must be in [0, 8]");
-  if ((uint64_t)o.pid_base + (uint64_t)P > 4294967296ull)
-    return fail(LX_E_INVALID, "pid_base + P exceeds 2^32 particle ids");
+  {
+    const uint64_t stride = o.pid_stride ? o.pid_stride : 1;
+    if (P > 0 && (uint64_t)o.pid_base + (uint64_t)(P - 1) * stride >= 4294967296ull)
+      return fail(LX_E_INVALID, "particle ids pid_base + p * pid_stride exceed 2^32");
+  }
   memset(prm, 0, sizeof(*prm));
   prm->t_start = o.t_start;
   prm->t_end = t_end;
@@ -306,6 +372,7 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
   prm->k0 = (uint32_t)o.seed;
   prm->k1 = (uint32_t)(o.seed >> 32) + o.rng_stream;
   prm->pid_base = o.pid_base;
+  prm->pid_stride = o.pid_stride ? o.pid_stride : 1;
   prm->n_c = o.n_c;
   prm->n_ssa_ex = o.n_ssa_ex;
   prm->n_ssa_im = o.n_ssa_im;
@@ -470,18 +537,10 @@ lx_status lx_simulate(lx_network net, int64_t P, const double* theta, const int3
   if (st != LX_OK) return st;
   long long grid = (P + block - 1) / block;
   if (batched) {
-    int dev = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return hip_fail(e, "device attributes");
-    // Active lanes per wave: full waves when the ensemble gives every SIMD
-    // (4 per CU) a wave, otherwise 32 or 16 so that more SIMDs are busy and
-    // each wave carries fewer divergent paths.
-    int lanes = o.lanes_per_wave;
-    if (lanes == 0) {
-      const long long simds = 4LL * cus;
-      lanes = P >= 64 * simds ? 64 : (P >= 32 * simds ? 32 : 16);
-    }
+    int cus = 0;
+    st = device_cus(&cus);
+    if (st != LX_OK) return st;
+    const int lanes = choose_lanes(o.lanes_per_wave, P, cus);
     const long long round = (long long)(block / 64) * lanes;
     const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
     long long per_block = (P + max_grid - 1) / max_grid;
@@ -498,6 +557,80 @@ lx_status lx_simulate(lx_network net, int64_t P, const double* theta, const int3
   hipError_t e = hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0, s,
                                        args, nullptr);
   if (e != hipSuccess) return hip_fail(e, batched ? "launch lx_sim_batched" : "launch lx_sim_plain");
+  return LX_OK;
+}
+
+lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, double eps,
+                          int32_t mode, const lx_options* opt, void* stream) {
+  if (K < 1 || K > lx::SET_MAX || !items) return fail(LX_E_INVALID, "need 1 <= K <= 8 items");
+  lx_options o;
+  if (opt) o = *opt;
+  else lx_options_default(&o);
+  o.schedule = LX_SCHED_BATCHED;
+  long long total = 0;
+  for (int k = 0; k < K; ++k) {
+    const lx_set_item& it = items[k];
+    if (!it.net || it.P < 0) return fail(LX_E_INVALID, "bad set item");
+    if (it.P > 0 && (!it.theta || !it.x0 || !it.x_out || !it.r_out || !it.G_out))
+      return fail(LX_E_INVALID, "null input/output pointer in set item");
+    lx_options ok = o;
+    ok.pid_base = it.pid_base;
+    ok.pid_stride = it.pid_stride;
+    lx::SimParams tmp;
+    lx_status st = fill_params(ok, it.P, t_end, eps, mode, &tmp);
+    if (st != LX_OK) return st;
+    total += it.P;
+  }
+  lx::SimParams prm;
+  lx_status st = fill_params(o, 0, t_end, eps, mode, &prm);
+  if (st != LX_OK) return st;
+  if (total == 0) return LX_OK;
+  const int block = o.block_size ? o.block_size : 256;
+  int cus = 0;
+  st = device_cus(&cus);
+  if (st != LX_OK) return st;
+  const int lanes = choose_lanes(o.lanes_per_wave, total, cus);
+  const long long round = (long long)(block / 64) * lanes;
+  const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
+  long long per_block = (total + max_grid - 1) / max_grid;
+  if (per_block < round) per_block = round;
+  lx::SetArgs args;
+  memset(&args, 0, sizeof(args));
+  args.K = K;
+  long long begin = 0;
+  std::vector<const lx_network_s*> nets;
+  std::ostringstream key;
+  key << "set/" << o.precision << "/" << block;
+  for (int k = 0; k < K; ++k) {
+    const lx_set_item& it = items[k];
+    lx::SetItem& d = args.it[k];
+    d.theta = it.theta;
+    d.x0 = it.x0;
+    d.x_out = it.x_out;
+    d.r_out = it.r_out;
+    d.G_out = it.G_out;
+    d.stats = (lx::Stats*)it.stats;
+    d.P = it.P;
+    d.per_block = per_block;
+    d.lanes = lanes;
+    d.pid_base = it.pid_base;
+    d.pid_stride = it.pid_stride ? it.pid_stride : 1;
+    d.block_begin = (int)begin;
+    d.blocks = (int)((it.P + per_block - 1) / per_block);
+    begin += d.blocks;
+    nets.push_back(it.net);
+    key << "/" << std::hex << fnv1a(it.net->netsrc) << std::dec;
+  }
+  if (begin > 0x7fffffffLL) return fail(LX_E_INVALID, "ensemble too large for one launch");
+  prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
+  hipFunction_t fn;
+  st = get_kernel_src(items[0].net, key.str(), [&]() { return set_source(nets, o.precision, block); },
+                      "lx_sim_set", &fn);
+  if (st != LX_OK) return st;
+  void* kargs[] = {(void*)&args, (void*)&prm};
+  hipError_t e = hipModuleLaunchKernel(fn, (unsigned)begin, 1, 1, (unsigned)block, 1, 1, 0,
+                                       (hipStream_t)stream, kargs, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "launch lx_sim_set");
   return LX_OK;
 }
 

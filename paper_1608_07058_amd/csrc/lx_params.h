@@ -21,7 +21,7 @@ struct SimParams {
   double eps, delta, n_stiff, k_ssa, k_crit, lam_thr, newton_tol;
   long long max_steps;
   long long P;
-  unsigned int k0, k1, pid_base;
+  unsigned int k0, k1, pid_base, pid_stride;
   int n_c, n_ssa_ex, n_ssa_im, newton_maxit, kcap, mode, accumulate;
   // batched scheduler
   long long per_block;    // particles owned by each block (contiguous range)
@@ -37,4 +37,22 @@ struct Stats {
       kclip, attempts;
 };
 
+// One network of a multi-network launch (lx_simulate_set).
+struct SetItem {
+  const double* theta;
+  const int* x0;
+  int* x_out;
+  int* r_out;
+  double* G_out;
+  Stats* stats;
+  long long P, per_block;
+  int block_begin, blocks, lanes, pad;
+  unsigned int pid_base, pid_stride;
+};
+
+constexpr int SET_MAX = 8;
+struct SetArgs {
+  int K, pad;
+  SetItem it[SET_MAX];
+};
 }  // namespace lx

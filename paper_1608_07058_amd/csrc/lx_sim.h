@@ -1,7 +1,8 @@
 // lx_sim.h -- network-specialised simulation of one trajectory per lane.
 //
 // Compiled at run time by hipRTC after lx_device.h, lx_params.h and a
-// generated block that defines namespace lxnet:
+// generated block that defines one traits struct per network (LxNet0, LxNet1,
+// ...; LxNet is the first) with static constexpr members:
 //   N, M         species and reactions (M <= 32 here)
 //   RO[M][N]     reactant orders m_ij
 //   NU[M][N]     net changes nu_ij = p_ij - m_ij
@@ -21,11 +22,6 @@
 
 namespace lx {
 
-using lxnet::M;
-using lxnet::N;
-
-static_assert(M <= 32, "reaction masks are 32-bit");
-
 __device__ __forceinline__ double binom_real(double y, int mult) {
   if (mult == 1) return y;
   if (mult == 2) return (y * (y - 1.0)) * 0.5;
@@ -39,31 +35,36 @@ __device__ __forceinline__ double binom_real_deriv(double y, int mult) {
 }
 
 // g_j(y) = prod over reactant species (ascending) of C(y_i, m_ij).
-__device__ __forceinline__ void g_all(const double (&y)[N], double (&g)[M]) {
+template <class NET>
+__device__ __forceinline__ void g_all(const double (&y)[NET::N], double (&g)[NET::M]) {
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
+  for (int j = 0; j < NET::M; ++j) {
     double gj = 1.0;
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-      if (lxnet::RO[j][i] > 0) gj = gj * binom_real(y[i], lxnet::RO[j][i]);
+    for (int i = 0; i < NET::N; ++i)
+      if (NET::RO[j][i] > 0) gj = gj * binom_real(y[i], NET::RO[j][i]);
     g[j] = gj;
   }
 }
 
 // d g_j / d y_k.
-__device__ __forceinline__ double dg_of(int j, int k, const double (&y)[N]) {
+template <class NET>
+__device__ __forceinline__ double dg_of(int j, int k, const double (&y)[NET::N]) {
   double gj = 1.0;
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    if (lxnet::RO[j][i] == 0) continue;
-    gj = gj * (i == k ? binom_real_deriv(y[i], lxnet::RO[j][i]) : binom_real(y[i], lxnet::RO[j][i]));
+  for (int i = 0; i < NET::N; ++i) {
+    if (NET::RO[j][i] == 0) continue;
+    gj = gj * (i == k ? binom_real_deriv(y[i], NET::RO[j][i]) : binom_real(y[i], NET::RO[j][i]));
   }
   return gj;
 }
 
-template <class P>
+template <class P, class NET>
 struct Lane {
   typedef typename P::R R;
+  static constexpr int N = NET::N;
+  static constexpr int M = NET::M;
+  static_assert(M <= 32, "reaction masks are 32-bit");
 
   // particle state
   u32 pid;
@@ -93,7 +94,7 @@ struct Lane {
   __device__ __forceinline__ void load(long long p, const double* __restrict__ theta,
                                        const int* __restrict__ x0, const int* r_in,
                                        const double* G_in, const SimParams& prm) {
-    pid = prm.pid_base + (u32)p;
+    pid = prm.pid_base + (u32)p * prm.pid_stride;
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -150,7 +151,7 @@ struct Lane {
       double xd[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) xd[i] = (double)x[i];
-      g_all(xd, g);
+      g_all<NET>(xd, g);
       gvalid = true;
     }
     a0 = (R)0;
@@ -163,7 +164,7 @@ struct Lane {
 
   // Factor phi_i of the highest-order reaction of species i (Cao 2006).
   __device__ __forceinline__ R phi(int i) const {
-    const int c = lxnet::PHI[i];
+    const int c = NET::PHI[i];
     if (c == 1) return (R)1;
     if (c == 2) return (R)2;
     if (c == 4) return (R)3;
@@ -180,11 +181,11 @@ struct Lane {
     R tau = P::inf();
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      if (lxnet::PHI[i] == 0) continue;
+      if (NET::PHI[i] == 0) continue;
       R mu = (R)0, s2 = (R)0;
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        const int v = lxnet::NU[j][i];
+        const int v = NET::NU[j][i];
         if (v == 0) continue;
         if ((use >> j) & 1u) {
           mu = mu + (R)v * a[j];
@@ -192,7 +193,7 @@ struct Lane {
         }
       }
       R num = eps * (R)x[i];
-      if (lxnet::PHI[i] != 1) num = num / phi(i);
+      if (NET::PHI[i] != 1) num = num / phi(i);
       const R bound = num < (R)1 ? (R)1 : num;
       const R t1 = (mu != (R)0) ? bound / P::fabs_(mu) : P::inf();
       const R t2 = (s2 != (R)0) ? (bound * bound) / s2 : P::inf();
@@ -219,7 +220,7 @@ struct Lane {
       int L = 0x7fffffff;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        const int v = lxnet::NU[j][i];
+        const int v = NET::NU[j][i];
         if (v < 0) {
           const int q = x[i] / (-v);
           L = q < L ? q : L;
@@ -238,12 +239,12 @@ struct Lane {
     *tau_ex_out = tau_ex;
     *tau_im_out = P::inf();
     *eq_out = 0;
-    if (lxnet::NPAIRS > 0 && prm.mode == MODE_ADAPTIVE) {
+    if (NET::NPAIRS > 0 && prm.mode == MODE_ADAPTIVE) {
       u32 eq = 0;
       const R delta = (R)prm.delta;
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        const int k = lxnet::PARTNER[j];
+        const int k = NET::PARTNER[j];
         if (k <= j) continue;
         if (((ncr >> j) & 1u) && ((ncr >> k) & 1u)) {
           const R lo = a[k] < a[j] ? a[k] : a[j];
@@ -306,7 +307,7 @@ struct Lane {
       if (j == jf) {
 #pragma unroll
         for (int i = 0; i < N; ++i)
-          if (lxnet::NU[j][i] != 0) x[i] = x[i] + lxnet::NU[j][i];
+          if (NET::NU[j][i] != 0) x[i] = x[i] + NET::NU[j][i];
         r[j] = r[j] + 1;
       }
     }
@@ -376,15 +377,15 @@ struct Lane {
       double ci = (double)x[i];
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        if (lxnet::NU[j][i] == 0) continue;
+        if (NET::NU[j][i] == 0) continue;
         if ((ncr >> j) & 1u) {
           const double d = (double)k[j] - tau * ax[j];
-          ci = ci + (double)lxnet::NU[j][i] * d;
+          ci = ci + (double)NET::NU[j][i] * d;
         }
       }
 #pragma unroll
       for (int j = 0; j < M; ++j)
-        if (lxnet::NU[j][i] != 0 && j == jc) ci = ci + (double)lxnet::NU[j][i];
+        if (NET::NU[j][i] != 0 && j == jc) ci = ci + (double)NET::NU[j][i];
       c[i] = ci;
       y[i] = (double)x[i];
     }
@@ -392,7 +393,7 @@ struct Lane {
     for (int it = 0; it < prm.newton_maxit; ++it) {
       n_nit += 1;
       double ay[M], gy[M];
-      g_all(y, gy);
+      g_all<NET>(y, gy);
 #pragma unroll
       for (int j = 0; j < M; ++j) ay[j] = ((ncr >> j) & 1u) ? th[j] * gy[j] : 0.0;
       double A[N][N], b[N];
@@ -401,7 +402,7 @@ struct Lane {
         double s = 0.0;
 #pragma unroll
         for (int j = 0; j < M; ++j)
-          if (lxnet::NU[j][i] != 0 && ((ncr >> j) & 1u)) s = s + (double)lxnet::NU[j][i] * ay[j];
+          if (NET::NU[j][i] != 0 && ((ncr >> j) & 1u)) s = s + (double)NET::NU[j][i] * ay[j];
         b[i] = -((y[i] - c[i]) - tau * s);
       }
 #pragma unroll
@@ -411,8 +412,8 @@ struct Lane {
           double s = 0.0;
 #pragma unroll
           for (int j = 0; j < M; ++j) {
-            if (lxnet::NU[j][i] == 0 || lxnet::RO[j][kk] == 0) continue;
-            if ((ncr >> j) & 1u) s = s + (double)lxnet::NU[j][i] * (th[j] * dg_of(j, kk, y));
+            if (NET::NU[j][i] == 0 || NET::RO[j][kk] == 0) continue;
+            if ((ncr >> j) & 1u) s = s + (double)NET::NU[j][i] * (th[j] * dg_of<NET>(j, kk, y));
           }
           A[i][kk] = (i == kk ? 1.0 : 0.0) - tau * s;
         }
@@ -438,7 +439,7 @@ struct Lane {
       return false;
     }
     double gy[M];
-    g_all(y, gy);
+    g_all<NET>(y, gy);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       if (!((ncr >> j) & 1u)) {
@@ -528,7 +529,7 @@ struct Lane {
         long long v = x[i];
 #pragma unroll
         for (int j = 0; j < M; ++j)
-          if (lxnet::NU[j][i] != 0) v = v + (long long)lxnet::NU[j][i] * k[j];
+          if (NET::NU[j][i] != 0) v = v + (long long)NET::NU[j][i] * k[j];
         xn[i] = v;
         ok = ok && v >= 0;
       }
@@ -550,7 +551,7 @@ struct Lane {
     double xd[N], gn[M];
 #pragma unroll
     for (int i = 0; i < N; ++i) xd[i] = (double)xn[i];
-    g_all(xd, gn);
+    g_all<NET>(xd, gn);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       G[j] = G[j] + (tau * (g[j] + gn[j])) * 0.5;
@@ -629,6 +630,7 @@ struct Lane {
 
 }  // namespace lx
 
+#if !defined(LX_BATCHED) && !defined(LX_SET)
 // Plain form: lane = particle for life, 64 lanes per wave.
 extern "C" __global__ void __launch_bounds__(LX_BLOCK)
     lx_sim_plain(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
@@ -636,37 +638,40 @@ extern "C" __global__ void __launch_bounds__(LX_BLOCK)
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= prm.P) return;
   const lx::Key key{prm.k0, prm.k1};
-  lx::Lane<LX_POLICY> lane;
+  lx::Lane<LX_POLICY, LxNet> lane;
   lane.load(p, theta, x0, r_out, G_out, prm);
   while (lane.active(prm)) lane.step(prm, key);
   lane.store(p, x_out, r_out, G_out, stats);
 }
+#endif
 
-#ifdef LX_BATCHED
-// Batched form.  Block b owns particles [b*per_block, (b+1)*per_block); its
-// waves run `lanes` active lanes each and refill a finished lane with the
+#if defined(LX_BATCHED) || defined(LX_SET)
+namespace lx {
+// Batched form.  Block `blk` owns particles [blk*per_block, (blk+1)*per_block);
+// its waves run `lanes` active lanes each and refill a finished lane with the
 // block's next particle through an LDS cursor (work stealing within the
 // block), until the range is exhausted.  Every iteration, lanes in an SSA
 // burst take up to ssa_k SSA steps while the other lanes plan and take one
 // leap attempt, which balances the divergent paths (an SSA step costs a
 // fraction of a leap).  Per trajectory the sequence of actions, and hence
 // every result, is the one of the plain form.
-extern "C" __global__ void __launch_bounds__(LX_BLOCK)
-    lx_sim_batched(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
-                   int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
-  __shared__ unsigned long long next;
+template <class NET>
+__device__ __forceinline__ void run_batched(long long blk, const double* __restrict__ theta,
+                                            const int* __restrict__ x0, int* x_out, int* r_out,
+                                            double* G_out, Stats* stats, const SimParams& prm,
+                                            unsigned long long* next) {
   const int lane_id = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int waves = blockDim.x >> 6;
-  const long long lo = (long long)blockIdx.x * prm.per_block;
+  const long long lo = blk * prm.per_block;
   long long hi = lo + prm.per_block;
   if (hi > prm.P) hi = prm.P;
-  if (threadIdx.x == 0) next = (unsigned long long)(lo + (long long)waves * prm.lanes);
+  if (threadIdx.x == 0) *next = (unsigned long long)(lo + (long long)waves * prm.lanes);
   __syncthreads();
-  const lx::Key key{prm.k0, prm.k1};
+  const Key key{prm.k0, prm.k1};
   long long p = lo + (long long)wave * prm.lanes + lane_id;
   bool has = lane_id < prm.lanes && p < hi;
-  lx::Lane<LX_POLICY> lane;
+  Lane<LX_POLICY, NET> lane;
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
   while (has) {
     if (lane.active(prm)) {
@@ -678,11 +683,22 @@ extern "C" __global__ void __launch_bounds__(LX_BLOCK)
     }
     if (!lane.active(prm)) {
       lane.store(p, x_out, r_out, G_out, stats);
-      p = (long long)atomicAdd(&next, 1ull);
+      p = (long long)atomicAdd(next, 1ull);
       has = p < hi;
       if (has) lane.load(p, theta, x0, r_out, G_out, prm);
     }
   }
+}
+
+}  // namespace lx
+#endif
+
+#ifdef LX_BATCHED
+extern "C" __global__ void __launch_bounds__(LX_BLOCK)
+    lx_sim_batched(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
+                   int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
+  __shared__ unsigned long long next;
+  lx::run_batched<LxNet>(blockIdx.x, theta, x0, x_out, r_out, G_out, stats, prm, &next);
 }
 #endif
 
@@ -695,7 +711,7 @@ extern "C" __global__ void __launch_bounds__(64)
   typedef LX_POLICY::R R;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= prm.P) return;
-  lx::Lane<LX_POLICY> lane;
+  lx::Lane<LX_POLICY, LxNet> lane;
   lx::SimParams p2 = prm;
   p2.accumulate = 0;
   p2.pid_base = 0;
@@ -704,7 +720,7 @@ extern "C" __global__ void __launch_bounds__(64)
   R tau_ex, tau_im;
   unsigned int eq;
   lane.decide(prm, &tau_ex, &tau_im, &eq);
-  for (int j = 0; j < lx::M; ++j) a_out[q * lx::M + j] = (double)lane.a[j];
+  for (int j = 0; j < LxNet::M; ++j) a_out[q * LxNet::M + j] = (double)lane.a[j];
   crit_out[q] = lane.crit;
   eq_out[q] = eq;
   tau_out[2 * q] = (double)tau_ex;
@@ -724,19 +740,19 @@ extern "C" __global__ void __launch_bounds__(64)
                      lx::SimParams prm) {
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= prm.P) return;
-  lx::Lane<lx::F64> lane;
+  lx::Lane<lx::F64, LxNet> lane;
   lx::SimParams p2 = prm;
   p2.accumulate = 0;
   p2.pid_base = 0;
   lane.load(q, theta, xs, nullptr, nullptr, p2);
   lane.propensities();
   lane.ncr = 0;
-  for (int j = 0; j < lx::M; ++j)
+  for (int j = 0; j < LxNet::M; ++j)
     if (lane.a[j] > 0.0 && j != jc[q]) lane.ncr |= 1u << j;
-  long long k[lx::M];
-  for (int j = 0; j < lx::M; ++j) k[j] = Pj[q * lx::M + j];
+  long long k[LxNet::M];
+  for (int j = 0; j < LxNet::M; ++j) k[j] = Pj[q * LxNet::M + j];
   const bool ok = lane.implicit_counts(tau[q], k, jc[q], prm);
-  for (int j = 0; j < lx::M; ++j) k_out[q * lx::M + j] = ok ? k[j] : 0;
+  for (int j = 0; j < LxNet::M; ++j) k_out[q * LxNet::M + j] = ok ? k[j] : 0;
   ok_out[q] = ok ? 1 : 0;
   it_out[q] = (int)lane.n_nit;
 }

@@ -26,12 +26,20 @@ EXPORTS = (
     "lx_options_default", "lx_last_error", "lx_network_create", "lx_network_prepare",
     "lx_network_destroy", "lx_network_info", "lx_simulate", "lx_test_philox",
     "lx_test_uniform_f64", "lx_test_uniform_f32", "lx_test_math", "lx_test_poisson",
-    "lx_test_exponential", "lx_test_tau_select", "lx_test_implicit",
+    "lx_test_exponential", "lx_test_tau_select", "lx_test_implicit", "lx_simulate_set",
 )
 
 
 class LxError(RuntimeError):
     pass
+
+
+class SetItem(C.Structure):
+    _fields_ = [
+        ("net", C.c_void_p), ("P", C.c_int64), ("theta", C.c_void_p), ("x0", C.c_void_p),
+        ("x_out", C.c_void_p), ("r_out", C.c_void_p), ("G_out", C.c_void_p),
+        ("stats", C.c_void_p), ("pid_base", C.c_uint32), ("pid_stride", C.c_uint32),
+    ]
 
 
 class Options(C.Structure):
@@ -43,7 +51,7 @@ class Options(C.Structure):
         ("n_ssa_ex", C.c_int32), ("n_ssa_im", C.c_int32), ("lambda_thr", C.c_double),
         ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("block_size", C.c_int32),
         ("max_steps", C.c_int64), ("lanes_per_wave", C.c_int32), ("ssa_k", C.c_int32),
-        ("blocks_per_cu", C.c_int32), ("reserved", C.c_int32 * 7),
+        ("blocks_per_cu", C.c_int32), ("pid_stride", C.c_uint32), ("reserved", C.c_int32 * 6),
     ]
 
 
@@ -74,6 +82,7 @@ def lib():
         L.lx_network_destroy.argtypes = [P]
         L.lx_network_info.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
         L.lx_simulate.argtypes = [P, I64, P, P, D, D, I32, C.POINTER(Options), P, P, P, P, P]
+        L.lx_simulate_set.argtypes = [I32, C.POINTER(SetItem), D, D, I32, C.POINTER(Options), P]
         L.lx_test_philox.argtypes = [I64, P, P, P, P]
         L.lx_test_uniform_f64.argtypes = [I64, P, P, P]
         L.lx_test_uniform_f32.argtypes = [I64, P, P, P]
@@ -200,6 +209,43 @@ def simulate(net: Network, theta, x0, t_end: float, eps: float = 0.03, mode="ada
                              MODES.get(mode, mode), C.byref(o), xo, ro, go, so,
                              _stream_ptr(stream)), "lx_simulate")
     return out
+
+
+def simulate_set(items, t_end: float, eps: float = 0.03, mode="adaptive", *, with_stats=True,
+                 stream=None, **opts):
+    """lx_simulate_set: ``items`` is a list of dicts with keys net, theta, x0
+    and optionally pid_base, pid_stride and out (preallocated x/r/G/stats).
+    Returns one output dict per item."""
+    import torch
+    arr = (SetItem * len(items))()
+    outs = []
+    for k, it in enumerate(items):
+        net, theta, x0 = it["net"], it["theta"], it["x0"]
+        P = theta.shape[0]
+        dev = theta.device
+        out = dict(it.get("out") or {})
+        out.setdefault("x", torch.empty((P, net.N), dtype=torch.int32, device=dev))
+        out.setdefault("r", torch.zeros((P, net.M), dtype=torch.int32, device=dev))
+        out.setdefault("G", torch.zeros((P, net.M), dtype=torch.float64, device=dev))
+        if with_stats:
+            out.setdefault("stats", torch.empty((P, STATS_WORDS), dtype=torch.int64, device=dev))
+        d = arr[k]
+        d.net = net.handle.value
+        d.P = P
+        d.theta = _dev(theta, torch.float64, (P, net.M), "theta").value
+        d.x0 = _dev(x0, torch.int32, (P, net.N), "x0").value
+        d.x_out = _dev(out["x"], torch.int32, (P, net.N), "x_out").value
+        d.r_out = _dev(out["r"], torch.int32, (P, net.M), "r_out").value
+        d.G_out = _dev(out["G"], torch.float64, (P, net.M), "G_out").value
+        d.stats = (_dev(out["stats"], torch.int64, (P, STATS_WORDS), "stats").value
+                   if with_stats else None)
+        d.pid_base = int(it.get("pid_base", 0))
+        d.pid_stride = int(it.get("pid_stride", 0))
+        outs.append(out)
+    o = options(**opts)
+    _check(lib().lx_simulate_set(len(items), arr, float(t_end), float(eps), MODES.get(mode, mode),
+                                 C.byref(o), _stream_ptr(stream)), "lx_simulate_set")
+    return outs
 
 
 def stats_numpy(stats_tensor) -> np.ndarray:

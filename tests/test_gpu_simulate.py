@@ -326,3 +326,57 @@ def test_distribution_dimer(lxm, orc, precision):
                   schedule="batched")
     ref = orc.simulate(net.m, net.p, theta, x0, 30.0, mode="adaptive", seed=4)
     _compare_distributions(got, ref, f"dimer/{precision}")
+
+
+# ---------------------------------------------------------------------------
+# Several networks in one launch (isomerisation / birth-death / Schloegl
+# interleaved 1:1:1, per-particle theta from Gamma priors).
+# ---------------------------------------------------------------------------
+
+def _set_run(lxm, wl, precision, **opts):
+    import torch
+    items = []
+    for k, net in enumerate(wl.nets):
+        items.append(dict(net=_handle(lxm, net),
+                          theta=torch.as_tensor(wl.theta[k], device="cuda"),
+                          x0=torch.as_tensor(wl.x0[k], device="cuda"),
+                          pid_base=k, pid_stride=len(wl.nets)))
+    outs = lxm.simulate_set(items, wl.t_end, wl.eps, wl.mode, precision=precision, **opts)
+    torch.cuda.synchronize()
+    return [{"x": o["x"].cpu().numpy(), "r": o["r"].cpu().numpy(), "G": o["G"].cpu().numpy(),
+             "stats": lxm.stats_numpy(o["stats"])} for o in outs]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_set_matches_oracle(lxm, orc, precision):
+    wl = W.mixed_set_workload(P=12000)
+    got = _set_run(lxm, wl, precision)
+    for k, net in enumerate(wl.nets):
+        ref = orc.simulate(net.m, net.p, wl.theta[k], wl.x0[k], wl.t_end, mode=wl.mode,
+                           precision=precision, pid_base=k, pid_stride=3)
+        assert_same(got[k], ref, f"{net.name}/{precision}")
+        # one network alone with the same ids gives the same result
+        alone = gpu_run(lxm, net, wl.theta[k], wl.x0[k], wl.t_end, wl.mode, precision=precision,
+                        schedule="batched", pid_base=k, pid_stride=3)
+        assert_same(alone, ref, f"{net.name} alone")
+
+
+def test_set_full_size_sampled(lxm, orc):
+    # The 2^20-particle mixed ensemble in one launch, checked on sampled
+    # particles of each network recomputed by the oracle.
+    wl = W.mixed_set_workload()
+    got = _set_run(lxm, wl, "mixed")
+    rng = np.random.default_rng(8)
+    for k, net in enumerate(wl.nets):
+        P = wl.theta[k].shape[0]
+        for q in np.concatenate([[0, P - 1], rng.choice(P, 12, replace=False)]):
+            pid = int(wl.pid[k][q])
+            ref = orc.simulate(net.m, net.p, wl.theta[k][q:q + 1], wl.x0[k][q:q + 1], wl.t_end,
+                               mode=wl.mode, precision="mixed", pid_base=pid)
+            one = {key: got[k][key][q:q + 1] for key in ("x", "r", "G", "stats")}
+            assert_same(one, ref, f"{net.name} particle {pid}")
+        st = got[k]["stats"]
+        assert np.all((st["status"] == 0) | (st["status"] == 4))
+        nu = (net.p - net.m).astype(np.int64)
+        ok = st["status"] == 0
+        assert np.array_equal(got[k]["x"][ok], wl.x0[k][ok] + got[k]["r"][ok].astype(np.int64) @ nu)
