@@ -92,6 +92,12 @@ def lib():
         L.orc_implicit.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int64, P, P, P, P, P,
                                    C.POINTER(Options), P, P, P, P]
         L.orc_implicit.restype = C.c_int
+        L.orc_gamma.argtypes = [C.c_int64, P, P, P, P, C.c_uint64, C.c_uint32, P]
+        L.orc_resample.argtypes = [C.c_int64, P, C.c_uint64, C.c_uint32, C.c_uint32, P]
+        L.orc_pf_run.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int64, C.c_int32, C.c_double,
+                                 C.c_int32, C.c_double, P, P, P, P, P, P, P, P,
+                                 C.POINTER(Options)]
+        L.orc_pf_run.restype = C.c_int
         assert L.orc_options_size() == C.sizeof(Options)
         assert L.orc_stats_size() == STATS_DTYPE.itemsize
         _lib = L
@@ -255,3 +261,49 @@ def implicit(m, p, theta, x, tau, Pj, jc, **kw):
     if rc != 0:
         raise ValueError("invalid network")
     return {"y": y, "k": k, "ok": ok.astype(bool), "iters": it}
+
+
+SITE_RESAMPLE = 0x40000002
+SITE_GAMMA = 0x40000010
+
+
+def gamma(shape, pid, e, j, *, seed=160807058, stream=0):
+    """Gamma(shape, 1) drawn at site (pid, e, SITE_GAMMA + j)."""
+    shape = np.ascontiguousarray(shape, dtype=np.float64).reshape(-1)
+    n = shape.shape[0]
+    bc = lambda v: np.ascontiguousarray(np.broadcast_to(v, n), dtype=np.uint32)
+    pid, e, j = bc(pid), bc(e), bc(j)
+    out = np.empty(n, np.float64)
+    lib().orc_gamma(n, _ptr(shape), _ptr(pid), _ptr(e), _ptr(j), seed, stream, _ptr(out))
+    return out
+
+
+def resample(codes, k, *, seed=160807058, stream=0):
+    """Ancestors of len(codes) new particles from integer weight codes."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint64)
+    anc = np.empty(codes.shape[0], np.int32)
+    lib().orc_resample(codes.shape[0], _ptr(codes), seed, stream, k, _ptr(anc))
+    return anc
+
+
+def pf_run(m, p, theta, x0, K, dt, obs_species, obs_sd, y, alpha, beta, **kw):
+    """Particle filter (see orc_pf_run); returns theta, x, r, G, loglik."""
+    m, p = _net_arrays(m, p)
+    M, N = m.shape
+    theta = np.array(theta, dtype=np.float64, copy=True)
+    x = np.array(x0, dtype=np.int32, copy=True)
+    P = theta.shape[0]
+    r = np.zeros((P, M), np.int32)
+    G = np.zeros((P, M), np.float64)
+    ll = np.empty(K, np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    kw.setdefault("nthreads", min(16, os.cpu_count() or 1))
+    o = options(**kw)
+    rc = lib().orc_pf_run(N, M, _ptr(m), _ptr(p), P, K, float(dt), obs_species, float(obs_sd),
+                          _ptr(y), _ptr(alpha), _ptr(beta), _ptr(theta), _ptr(x), _ptr(r),
+                          _ptr(G), _ptr(ll), C.byref(o))
+    if rc != 0:
+        raise ValueError(f"oracle particle filter failed ({rc})")
+    return {"theta": theta, "x": x, "r": r, "G": G, "loglik": ll}

@@ -44,6 +44,7 @@
 // its code nor its models nor numbers at these workloads are available.
 
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -951,6 +952,46 @@ struct Traj {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Particle-filter interval step (the paper's motivating use: particle-filter
+// Bayesian inference with the conjugate update Gamma(alpha + r, beta + G),
+// Background section).
+// ---------------------------------------------------------------------------
+const uint32_t SITE_RESAMPLE = 0x40000002u;
+const uint32_t SITE_GAMMA = 0x40000010u;  // + reaction index
+const double HALF_LOG_2PI_ = 0x1.d67f1c864beb5p-1;
+
+// Gamma(shape a >= 1, scale 1) by Marsaglia & Tsang (2000), with normal
+// variates from the polar method.  Trial t uses block 2t for the polar pair
+// and block 2t+1 for the acceptance uniform.
+double gamma_sample(double a, const Rng& rng, uint32_t e, uint32_t site) {
+  const double d = a - 1.0 / 3.0;
+  const double c = 1.0 / std::sqrt(9.0 * d);
+  uint32_t w[4];
+  for (uint32_t t = 0; t < 64; ++t) {
+    rng.block(e, site, 2 * t, w);
+    double U1 = uniform_f64(w[0], w[1]), U2 = uniform_f64(w[2], w[3]);
+    double u1 = 2.0 * U1 - 1.0, u2 = 2.0 * U2 - 1.0;
+    double s = u1 * u1 + u2 * u2;
+    if (s >= 1.0) continue;
+    double z = u1 * std::sqrt((-2.0 * log_f64(s)) / s);
+    double t1 = 1.0 + c * z;
+    if (t1 <= 0.0) continue;
+    double v = (t1 * t1) * t1;
+    rng.block(e, site, 2 * t + 1, w);
+    double u = uniform_f64(w[0], w[1]);
+    double zz = z * z;
+    if (u < 1.0 - 0.0331 * (zz * zz)) return d * v;
+    if (log_f64(u) < (((0.5 * zz) + d) - d * v) + d * log_f64(v)) return d * v;
+  }
+  return d;
+}
+
+// floor(U64 * S / 2^64) for the resampling draw: an exact integer in [0, S).
+uint64_t scale_u64(uint64_t r, uint64_t S) {
+  return (uint64_t)(((unsigned __int128)r * (unsigned __int128)S) >> 64);
+}
+
 template <class P>
 void run_range(const Net& net, const orc_options& o, double t_end, int64_t lo, int64_t hi,
                const double* theta, const int32_t* x0, int32_t* xo, int32_t* ro, double* Go,
@@ -1158,6 +1199,115 @@ int orc_implicit(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab,
     iters[q] = (int32_t)tr.st.newton_iters;
     for (int j = 0; j < M; ++j) k_out[q * M + j] = good ? tr.k[j] : 0;
     for (int i = 0; i < N; ++i) y_out[q * N + i] = good ? tr.ysol[i] : 0.0;
+  }
+  return 0;
+}
+
+
+// Gamma(shape[q], 1) at site (pid[q], e[q], SITE_GAMMA + j[q]) -- test hook.
+void orc_gamma(int64_t n, const double* shape, const uint32_t* pid, const uint32_t* e,
+               const uint32_t* j, uint64_t seed, uint32_t stream, double* out) {
+  Rng rng;
+  rng.key[0] = (uint32_t)seed;
+  rng.key[1] = (uint32_t)(seed >> 32) + stream;
+  for (int64_t q = 0; q < n; ++q) {
+    rng.pid = pid[q];
+    out[q] = gamma_sample(shape[q], rng, e[q], SITE_GAMMA + j[q]);
+  }
+}
+
+// Multinomial resampling from integer weight codes (test hook): ancestors of
+// P new particles at interval k.
+void orc_resample(int64_t P, const uint64_t* codes, uint64_t seed, uint32_t stream, uint32_t k,
+                  int32_t* anc) {
+  std::vector<uint64_t> S(P);
+  uint64_t acc = 0;
+  for (int64_t p = 0; p < P; ++p) { acc += codes[p]; S[p] = acc; }
+  Rng rng;
+  rng.key[0] = (uint32_t)seed;
+  rng.key[1] = (uint32_t)(seed >> 32) + stream;
+  for (int64_t q = 0; q < P; ++q) {
+    rng.pid = (uint32_t)q;
+    uint32_t w[4];
+    rng.block(k, SITE_RESAMPLE, 0, w);
+    uint64_t U = scale_u64(((uint64_t)w[0] << 32) | w[1], acc);
+    anc[q] = (int32_t)(std::upper_bound(S.begin(), S.end(), U) - S.begin());
+  }
+}
+
+// Particle filter over K observation intervals of length dt.  Per interval k
+// (1-based): every particle is simulated from (k-1) dt to k dt with r and G
+// accumulated (RNG stream k); its log-weight is the Gaussian log-density of
+// observation y[k-1] of species obs_species with sd obs_sd; weights become
+// integer codes floor(exp(lw - max lw) 2^40) (all 1 if every code is 0; lanes
+// with a non-OK status weigh 0); P ancestors are drawn by multinomial
+// resampling; the new particles take their ancestors' state and cumulative
+// r, G, and draw theta_j ~ Gamma(alpha_j + r_j, rate beta_j + G_j).  loglik[k-1]
+// = max lw + log(sum of codes 2^-40 / P).  theta, x, r, G are in/out.
+int orc_pf_run(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab, int64_t P,
+               int32_t K, double dt, int32_t obs_species, double obs_sd, const double* y,
+               const double* alpha, const double* beta, double* theta, int32_t* x, int32_t* r,
+               double* G, double* loglik, const orc_options* opt) {
+  Net net;
+  if (build_net(N, M, mtab, ptab, &net) != 0) return -1;
+  orc_options o = *opt;
+  o.accumulate = 1;
+  o.pid_base = 0;
+  o.pid_stride = 1;
+  std::vector<orc_stats> st(P);
+  std::vector<double> lw(P);
+  std::vector<uint64_t> code(P);
+  std::vector<int32_t> anc(P);
+  std::vector<int32_t> x2((size_t)P * N), r2((size_t)P * M);
+  std::vector<double> G2((size_t)P * M);
+  const double Lc = log_f64(obs_sd) + HALF_LOG_2PI_;
+  for (int k = 1; k <= K; ++k) {
+    o.t_start = (double)(k - 1) * dt;
+    o.rng_stream = opt->rng_stream + (uint32_t)k;
+    int rc = orc_simulate(N, M, mtab, ptab, P, theta, x, (double)k * dt, &o, x, r, G, st.data());
+    if (rc != 0) return rc;
+    double mx = -std::numeric_limits<double>::infinity();
+    for (int64_t p = 0; p < P; ++p) {
+      if (st[p].status != ST_OK) {
+        lw[p] = -std::numeric_limits<double>::infinity();
+        continue;
+      }
+      double dz = (y[k - 1] - (double)x[p * N + obs_species]) / obs_sd;
+      lw[p] = (-0.5 * (dz * dz)) - Lc;
+      mx = std::max(mx, lw[p]);
+    }
+    uint64_t S = 0;
+    for (int64_t p = 0; p < P; ++p) {
+      code[p] = (lw[p] == -std::numeric_limits<double>::infinity())
+                    ? 0
+                    : (uint64_t)std::floor(exp_f64(lw[p] - mx) * 0x1p40);
+      S += code[p];
+    }
+    if (S == 0) {  // every particle weighs zero: resample uniformly
+      loglik[k - 1] = -std::numeric_limits<double>::infinity();
+      for (int64_t p = 0; p < P; ++p) code[p] = 1;
+    } else {
+      loglik[k - 1] = mx + log_f64(((double)S * 0x1p-40) / (double)P);
+    }
+    orc_resample(P, code.data(), o.seed, opt->rng_stream, (uint32_t)k, anc.data());
+    Rng rng;
+    rng.key[0] = (uint32_t)o.seed;
+    rng.key[1] = (uint32_t)(o.seed >> 32) + opt->rng_stream;
+    for (int64_t q = 0; q < P; ++q) {
+      const int64_t a = anc[q];
+      for (int i = 0; i < N; ++i) x2[q * N + i] = x[a * N + i];
+      rng.pid = (uint32_t)q;
+      for (int j = 0; j < M; ++j) {
+        r2[q * M + j] = r[a * M + j];
+        G2[q * M + j] = G[a * M + j];
+        double shape = alpha[j] + (double)r2[q * M + j];
+        double rate = beta[j] + G2[q * M + j];
+        theta[q * M + j] = gamma_sample(shape, rng, (uint32_t)k, SITE_GAMMA + (uint32_t)j) / rate;
+      }
+    }
+    std::copy(x2.begin(), x2.end(), x);
+    std::copy(r2.begin(), r2.end(), r);
+    std::copy(G2.begin(), G2.end(), G);
   }
   return 0;
 }
