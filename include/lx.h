@@ -208,6 +208,62 @@ typedef struct lx_set_item {
 lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, double eps,
                           int32_t mode, const lx_options* opt, void* stream);
 
+/* ---- Particle filter over observation intervals ---------------------------
+ * The paper's motivating use (Background and Discussion sections): particle-
+ * filter Bayesian inference with the conjugate update theta_j | path ~
+ * Gamma(alpha_j + r_j, beta_j + G_j).  Interval k = 1..K covers
+ * [(k-1) dt, k dt]:
+ *   1. every particle is simulated over the interval (lx_simulate semantics,
+ *      r and G accumulated, RNG stream opt->rng_stream + k, particle id = row);
+ *   2. weight = Gaussian density of observation y[k-1] of species obs_species
+ *      with sd obs_sd; particles whose simulation failed weigh zero;
+ *   3. weights become integer codes floor(exp(lw - max lw) 2^40) (all equal if
+ *      every code is zero) and P ancestors are drawn by multinomial
+ *      resampling with exact integer prefix sums;
+ *   4. each new particle takes its ancestor's state and cumulative r, G and
+ *      draws theta_j ~ Gamma(alpha_j + r_j, rate beta_j + G_j);
+ *   5. loglik[k-1] = max lw + log(mean code 2^-40) (-inf if every weight is 0).
+ * All buffers are device memory owned by the caller; the workspace replaces
+ * any allocation by the library. */
+typedef struct lx_pf_problem {
+  lx_network net;
+  int64_t P;            /* particles, 1 .. 2^23 */
+  int32_t K;            /* observation intervals >= 1 */
+  int32_t obs_species;  /* observed species index */
+  double dt;            /* interval length > 0 */
+  double obs_sd;        /* observation noise sd > 0 */
+  const double* y;      /* [K] observations */
+  const double* alpha;  /* [M] prior shapes (>= 1: the Gamma sampler's range) */
+  const double* beta;   /* [M] prior rates (> 0) */
+  double* theta;        /* [P][M] in: initial parameters; out: last refresh */
+  int32_t* x;           /* [P][N] in: initial states; out: states at K dt */
+  int32_t* r;           /* [P][M] cumulative firing counts (normally zero at entry) */
+  double* G;            /* [P][M] cumulative integrals of g (normally zero at entry) */
+  double* loglik;       /* [K] log-likelihood increments */
+  void* workspace;      /* >= lx_pf_workspace_size bytes, 256-byte aligned */
+  size_t workspace_bytes;
+} lx_pf_problem;
+
+/* Bytes of workspace the filter needs for P particles of an N x M network. */
+lx_status lx_pf_workspace_size(int64_t P, int32_t N, int32_t M, size_t* bytes);
+
+/* Enqueue the K intervals on `stream` (direct launches).  eps, mode and opt as
+ * for lx_simulate (opt->t_start, accumulate, pid_base/stride are set by the
+ * filter). */
+lx_status lx_pf_run(const lx_pf_problem* pb, double eps, int32_t mode, const lx_options* opt,
+                    void* stream);
+
+/* A captured filter: all K intervals recorded once into a HIP graph on a
+ * non-default `stream` (capture happens during the call; nothing executes),
+ * then replayed by lx_pf_graph_launch on any stream.  The graph refers to the
+ * problem's buffers, which must outlive it.  Every replay runs the whole
+ * filter again from the buffers' current contents. */
+typedef struct lx_pf_graph_s* lx_pf_graph;
+lx_status lx_pf_graph_create(const lx_pf_problem* pb, double eps, int32_t mode,
+                             const lx_options* opt, void* stream, lx_pf_graph* out);
+lx_status lx_pf_graph_launch(lx_pf_graph g, void* stream);
+lx_status lx_pf_graph_destroy(lx_pf_graph g);
+
 /* ---- Test hooks: run the production device functions on fixed inputs. ----
  * All pointers are device memory; n elements; enqueued on stream. */
 
@@ -226,6 +282,11 @@ lx_status lx_test_math(int32_t fn, int64_t n, const void* in, void* out, void* s
 lx_status lx_test_poisson(int64_t n, const double* lam, const uint32_t* pid, const uint32_t* e,
                           const uint32_t* site, uint64_t seed, uint32_t stream_id,
                           double lambda_thr, int32_t precision, int64_t* out, void* stream);
+/* Gamma(shape[q], 1) at site (pid[q], e[q], Gamma site + j[q]) (the
+ * particle filter's refresh sampler); out double. */
+lx_status lx_test_gamma(int64_t n, const double* shape, const uint32_t* pid, const uint32_t* e,
+                        const uint32_t* j, uint64_t seed, uint32_t stream_id, double* out,
+                        void* stream);
 /* Exponential(1) = -log(U) at site (pid[q], e[q], SSA site). */
 lx_status lx_test_exponential(int64_t n, const uint32_t* pid, const uint32_t* e, uint64_t seed,
                               uint32_t stream_id, int32_t precision, double* out, void* stream);

@@ -45,6 +45,16 @@ hipError_t lxh_launch_poisson(long long, const double*, const unsigned*, const u
                               hipStream_t);
 hipError_t lxh_launch_exponential(long long, const unsigned*, const unsigned*, unsigned, unsigned,
                                   int, double*, hipStream_t);
+hipError_t lxh_launch_gamma(long long, const double*, const unsigned*, const unsigned*,
+                            const unsigned*, unsigned, unsigned, double*, hipStream_t);
+
+// Particle-filter kernels (lx_pf.hip).
+size_t lxpf_workspace_layout(long long P, int N, int M, char* base, lx::PfWork* w);
+hipError_t lxpf_launch_interval(long long P, int N, int M, int* x, int* r, double* G,
+                                double* theta, const double* y_k, int obs, double sd,
+                                const double* alpha, const double* beta, unsigned k0,
+                                unsigned k1, unsigned k, double* ll_k, const lx::PfWork& w,
+                                hipStream_t s);
 
 namespace {
 
@@ -383,6 +393,58 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
   return LX_OK;
 }
 
+// A resolved simulation launch: kernel, geometry and parameters.
+struct SimLaunch {
+  hipFunction_t fn = nullptr;
+  long long grid = 0;
+  int block = 0;
+  bool batched = false;
+  lx::SimParams prm;
+};
+
+lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end, double eps,
+                   int32_t mode, SimLaunch* L) {
+  lx_status st = fill_params(o, P, t_end, eps, mode, &L->prm);
+  if (st != LX_OK) return st;
+  if (P == 0) return LX_OK;
+  L->batched = o.schedule == LX_SCHED_BATCHED;
+  L->block = o.block_size ? o.block_size : (L->batched ? 256 : 64);
+  st = get_kernel(net, L->batched ? "batched" : "plain", o.precision, L->block,
+                  L->batched ? "lx_sim_batched" : "lx_sim_plain", &L->fn);
+  if (st != LX_OK) return st;
+  L->grid = (P + L->block - 1) / L->block;
+  if (L->batched) {
+    int cus = 0;
+    st = device_cus(&cus);
+    if (st != LX_OK) return st;
+    const int lanes = choose_lanes(o.lanes_per_wave, P, cus);
+    const long long round = (long long)(L->block / 64) * lanes;
+    const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
+    long long per_block = (P + max_grid - 1) / max_grid;
+    if (per_block < round) per_block = round;
+    L->prm.per_block = per_block;
+    L->prm.lanes = lanes;
+    L->prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
+    L->grid = (P + per_block - 1) / per_block;
+  }
+  if (L->grid > 0x7fffffffLL) return fail(LX_E_INVALID, "P too large for one launch");
+  return LX_OK;
+}
+
+lx_status launch_sim(const SimLaunch& L, const lx::SimParams& prm, const double* theta,
+                     const int32_t* x0, int32_t* x_out, int32_t* r_out, double* G_out,
+                     lx_stats* stats, hipStream_t s) {
+  lx::Stats* sp = (lx::Stats*)stats;
+  lx::SimParams p = prm;
+  void* args[] = {(void*)&theta, (void*)&x0, (void*)&x_out, (void*)&r_out,
+                  (void*)&G_out, (void*)&sp, (void*)&p};
+  hipError_t e = hipModuleLaunchKernel(L.fn, (unsigned)L.grid, 1, 1, (unsigned)L.block, 1, 1, 0,
+                                       s, args, nullptr);
+  if (e != hipSuccess)
+    return hip_fail(e, L.batched ? "launch lx_sim_batched" : "launch lx_sim_plain");
+  return LX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -522,42 +584,16 @@ lx_status lx_simulate(lx_network net, int64_t P, const double* theta, const int3
   lx_options o;
   if (opt) o = *opt;
   else lx_options_default(&o);
-  lx::SimParams prm;
-  lx_status st = fill_params(o, P, t_end, eps, mode, &prm);
+  lx::SimParams tmp;
+  lx_status st = fill_params(o, P, t_end, eps, mode, &tmp);
   if (st != LX_OK) return st;
   if (P == 0) return LX_OK;
   if (!theta || !x0 || !x_out || !r_out || !G_out)
     return fail(LX_E_INVALID, "null input/output pointer");
-  hipStream_t s = (hipStream_t)stream;
-  const bool batched = o.schedule == LX_SCHED_BATCHED;
-  const int block = o.block_size ? o.block_size : (batched ? 256 : 64);
-  hipFunction_t fn;
-  st = get_kernel(net, batched ? "batched" : "plain", o.precision, block,
-                  batched ? "lx_sim_batched" : "lx_sim_plain", &fn);
+  SimLaunch L;
+  st = plan_sim(net, P, o, t_end, eps, mode, &L);
   if (st != LX_OK) return st;
-  long long grid = (P + block - 1) / block;
-  if (batched) {
-    int cus = 0;
-    st = device_cus(&cus);
-    if (st != LX_OK) return st;
-    const int lanes = choose_lanes(o.lanes_per_wave, P, cus);
-    const long long round = (long long)(block / 64) * lanes;
-    const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
-    long long per_block = (P + max_grid - 1) / max_grid;
-    if (per_block < round) per_block = round;
-    prm.per_block = per_block;
-    prm.lanes = lanes;
-    prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
-    grid = (P + per_block - 1) / per_block;
-  }
-  if (grid > 0x7fffffffLL) return fail(LX_E_INVALID, "P too large for one launch");
-  lx::Stats* sp = (lx::Stats*)stats;
-  void* args[] = {(void*)&theta, (void*)&x0, (void*)&x_out, (void*)&r_out,
-                  (void*)&G_out, (void*)&sp, (void*)&prm};
-  hipError_t e = hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0, s,
-                                       args, nullptr);
-  if (e != hipSuccess) return hip_fail(e, batched ? "launch lx_sim_batched" : "launch lx_sim_plain");
-  return LX_OK;
+  return launch_sim(L, L.prm, theta, x0, x_out, r_out, G_out, stats, (hipStream_t)stream);
 }
 
 lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, double eps,
@@ -740,6 +776,144 @@ lx_status lx_test_implicit(lx_network net, int64_t Q, const double* theta, const
   hipError_t e = hipModuleLaunchKernel(fn, (unsigned)((Q + 63) / 64), 1, 1, 64, 1, 1, 0,
                                        (hipStream_t)stream, args, nullptr);
   return e == hipSuccess ? LX_OK : hip_fail(e, "implicit hook");
+}
+
+// ---------------------------------------------------------------------------
+// Particle filter.
+// ---------------------------------------------------------------------------
+lx_status lx_pf_workspace_size(int64_t P, int32_t N, int32_t M, size_t* bytes) {
+  if (!bytes || P < 1 || N < 1 || M < 1) return fail(LX_E_INVALID, "bad arguments");
+  *bytes = lxpf_workspace_layout(P, N, M, nullptr, nullptr);
+  return LX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+lx_status pf_check(const lx_pf_problem* pb, double eps, int32_t mode, const lx_options* opt,
+                   lx_options* o, SimLaunch* L, lx::PfWork* w) {
+  if (!pb || !pb->net) return fail(LX_E_INVALID, "null problem or network");
+  const lx_pf_problem& q = *pb;
+  if (q.P < 1 || q.P > (1LL << 23) || q.K < 1) return fail(LX_E_INVALID, "need 1 <= P <= 2^23, K >= 1");
+  if (q.obs_species < 0 || q.obs_species >= q.net->N) return fail(LX_E_INVALID, "bad obs_species");
+  if (!(q.dt > 0.0) || !std::isfinite(q.dt) || !(q.obs_sd > 0.0) || !std::isfinite(q.obs_sd))
+    return fail(LX_E_INVALID, "dt and obs_sd must be positive");
+  if (!q.y || !q.alpha || !q.beta || !q.theta || !q.x || !q.r || !q.G || !q.loglik || !q.workspace)
+    return fail(LX_E_INVALID, "null buffer");
+  const size_t need = lxpf_workspace_layout(q.P, q.net->N, q.net->M, nullptr, nullptr);
+  if (q.workspace_bytes < need || ((uintptr_t)q.workspace & 255u))
+    return fail(LX_E_INVALID, "workspace too small or not 256-byte aligned");
+  if (opt) *o = *opt;
+  else lx_options_default(o);
+  o->accumulate = 1;
+  o->pid_base = 0;
+  o->pid_stride = 1;
+  o->t_start = 0.0;
+  lx_status st = plan_sim(q.net, q.P, *o, q.dt, eps, mode, L);
+  if (st != LX_OK) return st;
+  lxpf_workspace_layout(q.P, q.net->N, q.net->M, (char*)q.workspace, w);
+  return LX_OK;
+}
+
+lx_status pf_enqueue(const lx_pf_problem& q, const lx_options& o, const SimLaunch& L,
+                     const lx::PfWork& w, hipStream_t s) {
+  for (int k = 1; k <= q.K; ++k) {
+    lx::SimParams prm = L.prm;
+    prm.t_start = (double)(k - 1) * q.dt;
+    prm.t_end = (double)k * q.dt;
+    prm.k1 = (uint32_t)(o.seed >> 32) + o.rng_stream + (uint32_t)k;
+    lx_status st = launch_sim(L, prm, q.theta, q.x, q.x, q.r, q.G, (lx_stats*)w.stats, s);
+    if (st != LX_OK) return st;
+    hipError_t e = lxpf_launch_interval(q.P, q.net->N, q.net->M, q.x, q.r, q.G, q.theta,
+                                        q.y + (k - 1), q.obs_species, q.obs_sd, q.alpha,
+                                        q.beta, (uint32_t)o.seed,
+                                        (uint32_t)(o.seed >> 32) + o.rng_stream, (unsigned)k,
+                                        q.loglik + (k - 1), w, s);
+    if (e != hipSuccess) return hip_fail(e, "particle-filter kernels");
+  }
+  return LX_OK;
+}
+
+}  // namespace
+
+struct lx_pf_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+lx_status lx_pf_run(const lx_pf_problem* pb, double eps, int32_t mode, const lx_options* opt,
+                    void* stream) {
+  lx_options o;
+  SimLaunch L;
+  lx::PfWork w;
+  lx_status st = pf_check(pb, eps, mode, opt, &o, &L, &w);
+  if (st != LX_OK) return st;
+  return pf_enqueue(*pb, o, L, w, (hipStream_t)stream);
+}
+
+lx_status lx_pf_graph_create(const lx_pf_problem* pb, double eps, int32_t mode,
+                             const lx_options* opt, void* stream, lx_pf_graph* out) {
+  if (!out) return fail(LX_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!stream) return fail(LX_E_INVALID, "graph capture needs a non-default stream");
+  lx_options o;
+  SimLaunch L;
+  lx::PfWork w;
+  lx_status st = pf_check(pb, eps, mode, opt, &o, &L, &w);  // compiles/loads before capture
+  if (st != LX_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  st = pf_enqueue(*pb, o, L, w, s);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(s, &graph);
+  if (st != LX_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  lx_pf_graph_s* g = new (std::nothrow) lx_pf_graph_s();
+  if (!g) {
+    (void)hipGraphDestroy(graph);
+    return fail(LX_E_NOMEM, "out of host memory");
+  }
+  g->graph = graph;
+  e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    delete g;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  *out = g;
+  return LX_OK;
+}
+
+lx_status lx_pf_graph_launch(lx_pf_graph g, void* stream) {
+  if (!g) return fail(LX_E_INVALID, "null graph");
+  hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  return e == hipSuccess ? LX_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+lx_status lx_pf_graph_destroy(lx_pf_graph g) {
+  if (!g) return LX_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return LX_OK;
+}
+
+lx_status lx_test_gamma(int64_t n, const double* shape, const uint32_t* pid, const uint32_t* e,
+                        const uint32_t* j, uint64_t seed, uint32_t stream_id, double* out,
+                        void* stream) {
+  if (n < 0 || (n > 0 && (!shape || !pid || !e || !j || !out)))
+    return fail(LX_E_INVALID, "bad arguments");
+  if (n == 0) return LX_OK;
+  hipError_t err = lxh_launch_gamma(n, shape, pid, e, j, (uint32_t)seed,
+                                    (uint32_t)(seed >> 32) + stream_id, out, (hipStream_t)stream);
+  return err == hipSuccess ? LX_OK : hip_fail(err, "gamma hook");
 }
 
 }  // extern "C"

@@ -282,4 +282,34 @@ __device__ __forceinline__ long long poisson_sample(typename P::R lam, typename 
   return poisson_ptrs<P>(lam, key, pid, e, site);
 }
 
+// ---------------------------------------------------------------------------
+// Gamma(a >= 1, scale 1): Marsaglia & Tsang (2000) with normal variates from
+// the polar method.  Trial t draws block 2t for the polar pair and block 2t+1
+// for the acceptance uniform.
+// ---------------------------------------------------------------------------
+constexpr u32 SITE_RESAMPLE = 0x40000002u;
+constexpr u32 SITE_GAMMA = 0x40000010u;  // + reaction index
+
+__device__ __noinline__ double gamma_sample(double a, const Key& key, u32 pid, u32 e, u32 site) {
+  const double d = a - 1.0 / 3.0;
+  const double c = 1.0 / __builtin_sqrt(9.0 * d);
+  for (u32 t = 0; t < 64; ++t) {
+    const Words4 w = draw_block(key, pid, e, site, 2 * t);
+    const double u1 = 2.0 * uniform_f64(w.w0, w.w1) - 1.0;
+    const double u2 = 2.0 * uniform_f64(w.w2, w.w3) - 1.0;
+    const double s = u1 * u1 + u2 * u2;
+    if (s >= 1.0) continue;
+    const double z = u1 * __builtin_sqrt((-2.0 * log_f64(s)) / s);
+    const double t1 = 1.0 + c * z;
+    if (t1 <= 0.0) continue;
+    const double v = (t1 * t1) * t1;
+    const Words4 w2 = draw_block(key, pid, e, site, 2 * t + 1);
+    const double u = uniform_f64(w2.w0, w2.w1);
+    const double zz = z * z;
+    if (u < 1.0 - 0.0331 * (zz * zz)) return d * v;
+    if (log_f64(u) < (((0.5 * zz) + d) - d * v) + d * log_f64(v)) return d * v;
+  }
+  return d;
+}
+
 }  // namespace lx

@@ -82,6 +82,13 @@ __global__ void __launch_bounds__(BLOCK)
   out[q] = (double)(-P::ulog(u1));
 }
 
+__global__ void __launch_bounds__(BLOCK)
+    gamma_kernel(long long n, const double* shape, const unsigned* pid, const unsigned* e,
+                 const unsigned* j, lx::Key key, double* out) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) out[q] = lx::gamma_sample(shape[q], key, pid[q], e[q], lx::SITE_GAMMA + j[q]);
+}
+
 static unsigned grid_of(long long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
 }  // namespace lxh
@@ -122,6 +129,14 @@ hipError_t lxh_launch_poisson(long long n, const double* lam, const unsigned* pi
   else
     hipLaunchKernelGGL(lxh::poisson_kernel<lx::F64>, dim3(lxh::grid_of(n)), dim3(lxh::BLOCK), 0,
                        s, n, lam, pid, e, site, key, lam_thr, kcap, out);
+  return hipGetLastError();
+}
+hipError_t lxh_launch_gamma(long long n, const double* shape, const unsigned* pid,
+                            const unsigned* e, const unsigned* j, unsigned k0, unsigned k1,
+                            double* out, hipStream_t s) {
+  const lx::Key key{k0, k1};
+  hipLaunchKernelGGL(lxh::gamma_kernel, dim3(lxh::grid_of(n)), dim3(lxh::BLOCK), 0, s, n, shape,
+                     pid, e, j, key, out);
   return hipGetLastError();
 }
 hipError_t lxh_launch_exponential(long long n, const unsigned* pid, const unsigned* e, unsigned k0,

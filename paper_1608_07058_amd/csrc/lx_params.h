@@ -55,4 +55,18 @@ struct SetArgs {
   int K, pad;
   SetItem it[SET_MAX];
 };
+// Particle-filter workspace pieces (lx_pf.hip), carved from the caller's buffer.
+struct PfWork {
+  int* x2;
+  int* r2;
+  double* G2;
+  double* lw;
+  unsigned long long* codes;
+  unsigned long long* scan;
+  Stats* stats;
+  double* bmax;
+  unsigned long long* bsum;
+  double* mx;
+  unsigned long long* total;
+};
 }  // namespace lx

@@ -1,0 +1,222 @@
+// lx_pf.hip -- particle-filter interval kernels (network independent).
+//
+// After every trajectory has been simulated over an observation interval
+// (lx_simulate with accumulated r and G), one interval of the filter is:
+//   1. log-weights: Gaussian log-density of the observed species, -inf for
+//      lanes whose simulation failed; per-block maxima;
+//   2. integer weight codes floor(exp(lw - max) 2^40) and per-block sums;
+//   3. inclusive prefix sums of the codes (exact uint64 arithmetic, so the
+//      result does not depend on the order of the parallel scan);
+//   4. multinomial resampling: particle q draws U in [0, S) from its Philox
+//      site and takes the smallest ancestor whose prefix sum exceeds U; it
+//      inherits the ancestor's state and cumulative r, G and draws
+//      theta_j ~ Gamma(alpha_j + r_j, rate beta_j + G_j) (the conjugate update
+//      of the paper's Background section);
+//   5. copy back and the interval's log-likelihood increment.
+#include <hip/hip_runtime.h>
+
+#include "lx_device.h"
+#include "lx_params.h"
+
+namespace lxpf {
+
+constexpr int BLOCK = 256;
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = sh[t + s] > sh[t] ? sh[t + s] : sh[t];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v,
+                                                        unsigned long long* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = sh[t] + sh[t + s];
+    __syncthreads();
+  }
+  const unsigned long long r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    logw_kernel(long long P, int N, const int* __restrict__ x, int obs, const double* y, double sd,
+                const lx::Stats* __restrict__ st, double* lw, double* bmax) {
+  __shared__ double sh[BLOCK];
+  const double Lc = lx::log_f64(sd) + 0x1.d67f1c864beb5p-1;  // log(sd) + log(2 pi)/2
+  const long long p = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  const double ninf = -__builtin_inf();
+  double v = ninf;
+  if (p < P && st[p].status == lx::LANE_OK) {
+    const double dz = (y[0] - (double)x[p * N + obs]) / sd;
+    v = (-0.5 * (dz * dz)) - Lc;
+  }
+  if (p < P) lw[p] = v;
+  const double m = block_max(v, sh);
+  if (threadIdx.x == 0) bmax[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    codes_kernel(long long P, const double* __restrict__ lw, const double* __restrict__ bmax,
+                 int nb, unsigned long long* codes, unsigned long long* bsum, double* mx_out) {
+  __shared__ double shd[BLOCK];
+  __shared__ unsigned long long shu[BLOCK];
+  double m = -__builtin_inf();
+  for (int b = threadIdx.x; b < nb; b += BLOCK) m = bmax[b] > m ? bmax[b] : m;
+  m = block_max(m, shd);
+  const long long p = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  unsigned long long c = 0;
+  if (p < P) {
+    const double v = lw[p];
+    if (v != -__builtin_inf())
+      c = (unsigned long long)__builtin_floor(lx::exp_f64(v - m) * 0x1p40);
+    codes[p] = c;
+  }
+  const unsigned long long s = block_sum(c, shu);
+  if (threadIdx.x == 0) {
+    bsum[blockIdx.x] = s;
+    if (blockIdx.x == 0) *mx_out = m;
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    scan_kernel(long long P, const unsigned long long* __restrict__ codes,
+                const unsigned long long* __restrict__ bsum, int nb, unsigned long long* scan,
+                unsigned long long* total_out) {
+  __shared__ unsigned long long sh[BLOCK];
+  unsigned long long off = 0, tot = 0;
+  for (int b = threadIdx.x; b < nb; b += BLOCK) {
+    if (b < (int)blockIdx.x) off += bsum[b];
+    tot += bsum[b];
+  }
+  off = block_sum(off, sh);
+  tot = block_sum(tot, sh);
+  const long long p = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  unsigned long long v = p < P ? codes[p] : 0ull;
+  // inclusive scan within the block (Hillis-Steele, exact integers)
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 1; s < BLOCK; s <<= 1) {
+    const unsigned long long add = threadIdx.x >= s ? sh[threadIdx.x - s] : 0ull;
+    __syncthreads();
+    sh[threadIdx.x] += add;
+    __syncthreads();
+  }
+  if (p < P) scan[p] = sh[threadIdx.x] + off;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *total_out = tot;
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    resample_kernel(long long P, int N, int M, const unsigned long long* __restrict__ scan,
+                    const unsigned long long* __restrict__ total_in, lx::Key key, unsigned k,
+                    const int* __restrict__ x, const int* __restrict__ r,
+                    const double* __restrict__ G, int* x2, int* r2, double* G2, double* theta,
+                    const double* __restrict__ alpha, const double* __restrict__ beta) {
+  const long long q = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (q >= P) return;
+  const unsigned long long S = *total_in;
+  const lx::Words4 w = lx::draw_block(key, (unsigned)q, k, lx::SITE_RESAMPLE, 0);
+  const unsigned long long r64 = ((unsigned long long)w.w0 << 32) | (unsigned long long)w.w1;
+  long long a;
+  if (S == 0) {  // every particle weighs zero: uniform resampling
+    a = (long long)__umul64hi(r64, (unsigned long long)P);
+  } else {
+    const unsigned long long U = __umul64hi(r64, S);
+    long long lo = 0, hi = P - 1;  // smallest a with scan[a] > U
+    while (lo < hi) {
+      const long long mid = (lo + hi) >> 1;
+      if (scan[mid] > U) hi = mid;
+      else lo = mid + 1;
+    }
+    a = lo;
+  }
+  for (int i = 0; i < N; ++i) x2[q * N + i] = x[a * N + i];
+  for (int j = 0; j < M; ++j) {
+    const int rj = r[a * M + j];
+    const double Gj = G[a * M + j];
+    r2[q * M + j] = rj;
+    G2[q * M + j] = Gj;
+    const double shape = alpha[j] + (double)rj;
+    const double rate = beta[j] + Gj;
+    theta[q * M + j] = lx::gamma_sample(shape, key, (unsigned)q, k, lx::SITE_GAMMA + (unsigned)j) / rate;
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    copyback_kernel(long long P, int N, int M, const int* __restrict__ x2,
+                    const int* __restrict__ r2, const double* __restrict__ G2, int* x, int* r,
+                    double* G, const double* mx, const unsigned long long* total, double* ll) {
+  const long long q = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (q < P) {
+    for (int i = 0; i < N; ++i) x[q * N + i] = x2[q * N + i];
+    for (int j = 0; j < M; ++j) {
+      r[q * M + j] = r2[q * M + j];
+      G[q * M + j] = G2[q * M + j];
+    }
+  }
+  if (q == 0) {
+    const unsigned long long S = *total;
+    ll[0] = S == 0 ? -__builtin_inf()
+                   : *mx + lx::log_f64(((double)S * 0x1p-40) / (double)P);
+  }
+}
+
+}  // namespace lxpf
+
+// Workspace layout (256-byte aligned pieces).
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t lxpf_workspace_layout(long long P, int N, int M, char* base, lx::PfWork* w) {
+  const long long nb = (P + lxpf::BLOCK - 1) / lxpf::BLOCK;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  lx::PfWork t;
+  t.x2 = (int*)take((size_t)P * N * 4);
+  t.r2 = (int*)take((size_t)P * M * 4);
+  t.G2 = (double*)take((size_t)P * M * 8);
+  t.lw = (double*)take((size_t)P * 8);
+  t.codes = (unsigned long long*)take((size_t)P * 8);
+  t.scan = (unsigned long long*)take((size_t)P * 8);
+  t.stats = (lx::Stats*)take((size_t)P * sizeof(lx::Stats));
+  t.bmax = (double*)take((size_t)nb * 8);
+  t.bsum = (unsigned long long*)take((size_t)nb * 8);
+  t.mx = (double*)take(8);
+  t.total = (unsigned long long*)take(8);
+  if (w) *w = t;
+  return off;
+}
+
+// Enqueue steps 1-5 of interval k (1-based) on stream s.
+hipError_t lxpf_launch_interval(long long P, int N, int M, int* x, int* r, double* G,
+                                double* theta, const double* y_k, int obs, double sd,
+                                const double* alpha, const double* beta, unsigned k0,
+                                unsigned k1, unsigned k, double* ll_k, const lx::PfWork& w,
+                                hipStream_t s) {
+  const unsigned nb = (unsigned)((P + lxpf::BLOCK - 1) / lxpf::BLOCK);
+  const dim3 g(nb), b(lxpf::BLOCK);
+  hipLaunchKernelGGL(lxpf::logw_kernel, g, b, 0, s, P, N, x, obs, y_k, sd, w.stats, w.lw,
+                     w.bmax);
+  hipLaunchKernelGGL(lxpf::codes_kernel, g, b, 0, s, P, w.lw, w.bmax, (int)nb, w.codes, w.bsum,
+                     w.mx);
+  hipLaunchKernelGGL(lxpf::scan_kernel, g, b, 0, s, P, w.codes, w.bsum, (int)nb, w.scan, w.total);
+  const lx::Key key{k0, k1};
+  hipLaunchKernelGGL(lxpf::resample_kernel, g, b, 0, s, P, N, M, w.scan, w.total, key, k, x, r, G,
+                     w.x2, w.r2, w.G2, theta, alpha, beta);
+  hipLaunchKernelGGL(lxpf::copyback_kernel, g, b, 0, s, P, N, M, w.x2, w.r2, w.G2, x, r, G, w.mx,
+                     w.total, ll_k);
+  return hipGetLastError();
+}

@@ -27,11 +27,23 @@ EXPORTS = (
     "lx_network_destroy", "lx_network_info", "lx_simulate", "lx_test_philox",
     "lx_test_uniform_f64", "lx_test_uniform_f32", "lx_test_math", "lx_test_poisson",
     "lx_test_exponential", "lx_test_tau_select", "lx_test_implicit", "lx_simulate_set",
+    "lx_pf_workspace_size", "lx_pf_run", "lx_pf_graph_create", "lx_pf_graph_launch",
+    "lx_pf_graph_destroy", "lx_test_gamma",
 )
 
 
 class LxError(RuntimeError):
     pass
+
+
+class PfProblem(C.Structure):
+    _fields_ = [
+        ("net", C.c_void_p), ("P", C.c_int64), ("K", C.c_int32), ("obs_species", C.c_int32),
+        ("dt", C.c_double), ("obs_sd", C.c_double), ("y", C.c_void_p), ("alpha", C.c_void_p),
+        ("beta", C.c_void_p), ("theta", C.c_void_p), ("x", C.c_void_p), ("r", C.c_void_p),
+        ("G", C.c_void_p), ("loglik", C.c_void_p), ("workspace", C.c_void_p),
+        ("workspace_bytes", C.c_size_t),
+    ]
 
 
 class SetItem(C.Structure):
@@ -83,6 +95,13 @@ def lib():
         L.lx_network_info.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
         L.lx_simulate.argtypes = [P, I64, P, P, D, D, I32, C.POINTER(Options), P, P, P, P, P]
         L.lx_simulate_set.argtypes = [I32, C.POINTER(SetItem), D, D, I32, C.POINTER(Options), P]
+        L.lx_pf_workspace_size.argtypes = [I64, I32, I32, C.POINTER(C.c_size_t)]
+        L.lx_pf_run.argtypes = [C.POINTER(PfProblem), D, I32, C.POINTER(Options), P]
+        L.lx_pf_graph_create.argtypes = [C.POINTER(PfProblem), D, I32, C.POINTER(Options), P,
+                                         C.POINTER(C.c_void_p)]
+        L.lx_pf_graph_launch.argtypes = [P, P]
+        L.lx_pf_graph_destroy.argtypes = [P]
+        L.lx_test_gamma.argtypes = [I64, P, P, P, P, U64, U32, P, P]
         L.lx_test_philox.argtypes = [I64, P, P, P, P]
         L.lx_test_uniform_f64.argtypes = [I64, P, P, P]
         L.lx_test_uniform_f32.argtypes = [I64, P, P, P]
@@ -246,6 +265,90 @@ def simulate_set(items, t_end: float, eps: float = 0.03, mode="adaptive", *, wit
     _check(lib().lx_simulate_set(len(items), arr, float(t_end), float(eps), MODES.get(mode, mode),
                                  C.byref(o), _stream_ptr(stream)), "lx_simulate_set")
     return outs
+
+
+class ParticleFilter:
+    """lx_pf_*: particle filter over K observation intervals on device tensors.
+
+    theta [P][M] f64, x [P][N] i32 (updated in place), y [K], alpha/beta [M].
+    Allocates r, G, loglik and the workspace with torch.  ``run()`` enqueues
+    direct launches; ``capture(stream)`` records a HIP graph once and
+    ``replay(stream)`` launches it.
+    """
+
+    def __init__(self, net, theta, x, y, alpha, beta, dt, obs_species, obs_sd, eps=0.03,
+                 mode="adaptive", **opts):
+        import torch
+        self.net = net
+        P, K = theta.shape[0], y.shape[0]
+        dev = theta.device
+        self.theta, self.x = theta, x
+        self.y = y.to(torch.float64).contiguous()
+        self.alpha = alpha.to(torch.float64).contiguous()
+        self.beta = beta.to(torch.float64).contiguous()
+        self.r = torch.zeros((P, net.M), dtype=torch.int32, device=dev)
+        self.G = torch.zeros((P, net.M), dtype=torch.float64, device=dev)
+        self.loglik = torch.empty(K, dtype=torch.float64, device=dev)
+        nb = C.c_size_t()
+        _check(lib().lx_pf_workspace_size(P, net.N, net.M, C.byref(nb)), "lx_pf_workspace_size")
+        self.work = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
+        base = self.work.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        pb = PfProblem()
+        pb.net = net.handle.value
+        pb.P, pb.K, pb.obs_species = P, K, obs_species
+        pb.dt, pb.obs_sd = float(dt), float(obs_sd)
+        pb.y = _dev(self.y, torch.float64, (K,), "y").value
+        pb.alpha = _dev(self.alpha, torch.float64, (net.M,), "alpha").value
+        pb.beta = _dev(self.beta, torch.float64, (net.M,), "beta").value
+        pb.theta = _dev(theta, torch.float64, (P, net.M), "theta").value
+        pb.x = _dev(x, torch.int32, (P, net.N), "x").value
+        pb.r = self.r.data_ptr()
+        pb.G = self.G.data_ptr()
+        pb.loglik = self.loglik.data_ptr()
+        pb.workspace = aligned
+        pb.workspace_bytes = nb.value
+        self.pb = pb
+        self.eps, self.mode = float(eps), MODES.get(mode, mode)
+        self.opts = options(**opts)
+        self.graph = C.c_void_p()
+
+    def run(self, stream=None):
+        _check(lib().lx_pf_run(C.byref(self.pb), self.eps, self.mode, C.byref(self.opts),
+                               _stream_ptr(stream)), "lx_pf_run")
+
+    def capture(self, stream):
+        self.release()
+        _check(lib().lx_pf_graph_create(C.byref(self.pb), self.eps, self.mode, C.byref(self.opts),
+                                        _stream_ptr(stream), C.byref(self.graph)),
+               "lx_pf_graph_create")
+
+    def replay(self, stream=None):
+        _check(lib().lx_pf_graph_launch(self.graph, _stream_ptr(stream)), "lx_pf_graph_launch")
+
+    def release(self):
+        if self.graph.value:
+            lib().lx_pf_graph_destroy(self.graph)
+            self.graph = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def test_gamma(shape, pid, e, j, *, seed=160807058, stream_id=0, device="cuda"):
+    import torch
+    shape = np.asarray(shape, np.float64).reshape(-1)
+    n = shape.shape[0]
+    u = lambda v: _t(np.broadcast_to(np.asarray(v, np.uint32), n).view(np.int32), torch.int32, device)
+    st = _t(shape, torch.float64, device)
+    pt, et, jt = u(pid), u(e), u(j)
+    out = torch.empty(n, dtype=torch.float64, device=device)
+    _check(lib().lx_test_gamma(n, _ptr(st), _ptr(pt), _ptr(et), _ptr(jt), seed, stream_id,
+                               _ptr(out), _stream_ptr(None)), "lx_test_gamma")
+    return out.cpu().numpy()
 
 
 def stats_numpy(stats_tensor) -> np.ndarray:

@@ -1,0 +1,138 @@
+"""Particle filter on the GPU (lx_pf_*) against the oracle's filter.
+
+The filter's floating point decides integers (weight codes, ancestors,
+Gamma draws feed the next interval), so the kernels use the same operation
+sequences and integer prefix sums as the oracle and the results are compared
+exactly: theta, states, cumulative r and G and the log-likelihood increments.
+Graph replays must reproduce the direct launches on every replay.
+"""
+
+import numpy as np
+import pytest
+
+from paper_1608_07058_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lxm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_07058_amd import lx
+    lx.lib()
+    return lx
+
+
+def _observations(K, seed=3):
+    # stand-in observations of the protein level (the filter's input)
+    rng = np.random.default_rng(seed)
+    return np.clip(100.0 + np.cumsum(rng.normal(0.0, 15.0, K)), 0.0, None)
+
+
+def _filter(lxm, net, theta, x0, y, dt, **opts):
+    import torch
+    h = lxm.Network(net.m, net.p)
+    th = torch.as_tensor(theta.copy(), device="cuda")
+    xx = torch.as_tensor(x0.copy(), device="cuda")
+    alpha = torch.full((net.M,), 2.0, dtype=torch.float64, device="cuda")
+    beta = torch.as_tensor(2.0 / net.theta, device="cuda")
+    pf = lxm.ParticleFilter(h, th, xx, torch.as_tensor(y, device="cuda"), alpha, beta, dt, 3,
+                            10.0, **opts)
+    return h, pf
+
+
+def _get(pf):
+    import torch
+    torch.cuda.synchronize()
+    return {"theta": pf.theta.cpu().numpy(), "x": pf.x.cpu().numpy(), "r": pf.r.cpu().numpy(),
+            "G": pf.G.cpu().numpy(), "loglik": pf.loglik.cpu().numpy()}
+
+
+def _same(got, ref, what):
+    for k in ("theta", "x", "r", "G", "loglik"):
+        assert np.array_equal(got[k], ref[k]), (what, k)
+
+
+def test_gamma_hook_bit_exact(lxm, orc):
+    rng = np.random.default_rng(1)
+    shape = np.concatenate([np.full(5000, 1.0), rng.uniform(1, 50, 20000), 10 ** rng.uniform(2, 6, 5000)])
+    n = shape.shape[0]
+    pid = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    e = rng.integers(0, 100, n).astype(np.uint32)
+    j = rng.integers(0, 16, n).astype(np.uint32)
+    assert np.array_equal(lxm.test_gamma(shape, pid, e, j), orc.gamma(shape, pid, e, j))
+
+
+@pytest.mark.parametrize("schedule,precision", [("batched", "mixed"), ("plain", "fp64")])
+def test_filter_matches_oracle(lxm, orc, schedule, precision):
+    net = W.telegraph()
+    P, K = 4096 + 37, 12
+    theta = W.gamma_prior_theta(net, P, seed=5)
+    _, x0 = W.tile(net, P)
+    y = _observations(K)
+    h, pf = _filter(lxm, net, theta, x0, y, 5.0, schedule=schedule, precision=precision)
+    pf.run()
+    got = _get(pf)
+    ref = orc.pf_run(net.m, net.p, theta, x0, K, 5.0, 3, 10.0, y, np.full(net.M, 2.0),
+                     2.0 / net.theta, precision=precision)
+    _same(got, ref, f"{schedule}/{precision}")
+    assert np.all(np.isfinite(got["loglik"]))
+
+
+def test_filter_graph_replays_match_direct_launches(lxm, orc):
+    import torch
+    net = W.telegraph()
+    P, K = 2048, 6
+    theta = W.gamma_prior_theta(net, P, seed=6)
+    _, x0 = W.tile(net, P)
+    y = _observations(K, seed=4)
+    ref = orc.pf_run(net.m, net.p, theta, x0, K, 5.0, 3, 10.0, y, np.full(net.M, 2.0),
+                     2.0 / net.theta, precision="mixed")
+    h, pf = _filter(lxm, net, theta, x0, y, 5.0, schedule="batched", precision="mixed")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pf.capture(s)
+    th0 = torch.as_tensor(theta, device="cuda")
+    xx0 = torch.as_tensor(x0, device="cuda")
+    for rep in range(3):
+        # eager resets between replays (copies, not memsets inside the graph)
+        pf.theta.copy_(th0)
+        pf.x.copy_(xx0)
+        pf.r.zero_()
+        pf.G.zero_()
+        torch.cuda.synchronize()
+        pf.replay(s)
+        s.synchronize()
+        _same(_get(pf), ref, f"replay {rep}")
+    pf.release()
+
+
+def test_filter_full_size_runs(lxm):
+    # The particle-filter workload's shape: 2^18 particles; a few intervals here
+    # (the full 50 run in the benchmark-style check below).
+    import torch
+    wl = W.telegraph_workload()
+    net = wl.nets[0]
+    K = 50
+    y = _observations(K, seed=9)
+    h, pf = _filter(lxm, net, wl.theta[0], wl.x0[0], y, 5.0, schedule="batched",
+                    precision="mixed")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pf.capture(s)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(s)
+    pf.replay(s)
+    end.record(s)
+    s.synchronize()
+    out = _get(pf)
+    ms = start.elapsed_time(end)
+    print(f"particle filter 2^18 particles x 50 intervals: {ms:.1f} ms")
+    assert np.all(np.isfinite(out["loglik"]))
+    assert np.all(out["theta"] > 0)
+    nu = (net.p - net.m).astype(np.int64)
+    assert np.array_equal(out["x"], wl.x0[0] + out["r"].astype(np.int64) @ nu)
+    assert np.allclose(out["G"][:, 0] + out["G"][:, 1], 250.0, rtol=1e-12)
+    pf.release()
