@@ -96,38 +96,37 @@ def telegraph() -> Network:
                 ("on", "off", "transcribe", "mRNA decay", "translate", "protein decay"))
 
 
-def random_network(seed=4, N=48, M=128, n_pairs=32, frac_uni=0.4, omega=1.0) -> Network:
-    """Seeded random mass-action network (large-network workload).
+def random_network(seed=4, N=48, M=128, n_pairs=32, frac_uni=0.4, omega=100.0,
+                   fast=(1.0, 1e2), slow=(1e-3, 1e-1)) -> Network:
+    """Seeded random stiff mass-action network (large-network workload).
 
-    40 % unimolecular / 60 % bimolecular reactions (2A allowed), products of
-    1-2 species with coefficients 1-2.  Species get masses w in {1,2,3}; every
-    reaction satisfies w.p <= w.m so populations stay bounded, and ``n_pairs``
-    reversible pairs with w.p == w.m give partial equilibria.  Rate constants
-    are log-uniform on [1e-3, 1e2]; bimolecular constants are divided by the
-    system size ``omega``.  x0 is uniform on {50..500}.
+    N species, M reactions, 40 % unimolecular and 60 % bimolecular (2A
+    allowed); products are 1-2 species with coefficients 1-2.  Species get
+    masses w in {1, 2, 3}; every reaction satisfies w.p <= w.m, so the total
+    mass never grows, and ``n_pairs`` reversible pairs conserve it exactly.
+    Stiffness: the pairs are fast (rate constants log-uniform on ``fast``),
+    the other reactions slow (log-uniform on ``slow``), all within
+    [1e-3, 1e2]; bimolecular constants are divided by the system size
+    ``omega``.  x0 is uniform on {50..500}.
     """
     rng = np.random.default_rng(seed)
     w = rng.integers(1, 4, size=N)
     m = np.zeros((M, N), np.int32)
     p = np.zeros((M, N), np.int32)
-    j = 0
 
     def draw_reactants(bi):
         r = np.zeros(N, np.int32)
         if not bi:
             r[rng.integers(N)] = 1
         else:
-            a, b = rng.integers(N), rng.integers(N)
-            r[a] += 1
-            r[b] += 1
+            r[rng.integers(N)] += 1
+            r[rng.integers(N)] += 1
         return r
 
     def draw_products(mass, exact):
-        # products of 1-2 species, coefficients 1-2, total mass <= mass (== if exact)
-        for _ in range(2000):
+        for _ in range(5000):
             q = np.zeros(N, np.int32)
-            ns = rng.integers(1, 3)
-            for _s in range(ns):
+            for _s in range(rng.integers(1, 3)):
                 q[rng.integers(N)] += rng.integers(1, 3)
             pm = int(w @ q)
             if (exact and pm == mass) or (not exact and pm <= mass):
@@ -137,31 +136,27 @@ def random_network(seed=4, N=48, M=128, n_pairs=32, frac_uni=0.4, omega=1.0) -> 
     n_uni = int(round(frac_uni * M))
     kinds = np.array([0] * n_uni + [1] * (M - n_uni))
     rng.shuffle(kinds)
-    # reversible pairs first (each uses two reaction slots)
-    pairs = []
-    while len(pairs) < n_pairs:
-        bi = bool(kinds[2 * len(pairs)])
-        r = draw_reactants(bi)
+    rows = []
+    fast_rows = []
+    # reversible pairs: the reverse reaction consumes exactly the products
+    while len(fast_rows) < 2 * n_pairs:
+        r = draw_reactants(bool(kinds[len(rows)]))
         q = draw_products(int(w @ r), exact=True)
-        if q is None or np.array_equal(q, r):
+        if q is None or np.array_equal(q, r) or q.sum() > 2:
             continue
-        # the reverse reaction must have order <= 3 and consume exactly q
-        if q.sum() > 2:
-            continue
-        pairs.append((r, q))
-    for r, q in pairs:
-        m[j], p[j] = r, q
-        m[j + 1], p[j + 1] = q, r
-        j += 2
-    while j < M:
-        bi = bool(kinds[j])
-        r = draw_reactants(bi)
+        fast_rows += [len(rows), len(rows) + 1]
+        rows += [(r, q), (q, r)]
+    while len(rows) < M:
+        r = draw_reactants(bool(kinds[len(rows)]))
         q = draw_products(int(w @ r), exact=False)
         if q is None or np.array_equal(q, r):
             continue
+        rows.append((r, q))
+    for j, (r, q) in enumerate(rows):
         m[j], p[j] = r, q
-        j += 1
-    theta = 10.0 ** rng.uniform(-3.0, 2.0, size=M)
+    theta = 10.0 ** rng.uniform(np.log10(slow[0]), np.log10(slow[1]), size=M)
+    fr = np.array(fast_rows)
+    theta[fr] = 10.0 ** rng.uniform(np.log10(fast[0]), np.log10(fast[1]), size=len(fr))
     order = m.sum(axis=1)
     theta = np.where(order >= 2, theta / omega, theta)
     x0 = rng.integers(50, 501, size=N)
