@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--untuned", action="store_true", help="ignore autotuned batched knobs")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes --steps times "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -73,7 +74,12 @@ def log(args, *a):
 
 def time_form(args, lx, h, theta, x0, wl, form, out):
     import torch
+    from paper_1608_07058_amd import autotune
     opts = dict(FORMS[form])
+    if opts["schedule"] == "batched" and not args.untuned:
+        # knobs found by paper_1608_07058_amd/autotune.py for this ensemble, if any
+        net = wl.nets[0]
+        opts.update(autotune.lookup(net.m, net.p, wl.P, opts["precision"], wl.mode))
     if args.block_size:
         opts["block_size"] = args.block_size
     stream = torch.cuda.current_stream()
@@ -107,6 +113,7 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
         "lane_status_ok": bool((stats["status"] == 0).all()),
         "precision": opts["precision"],
         "schedule": opts["schedule"],
+        "options": {k: v for k, v in opts.items() if k not in ("precision", "schedule")},
     }
 
 

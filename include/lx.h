@@ -99,7 +99,7 @@ typedef struct lx_options {
   int32_t newton_maxit; /* default 20 */
   int32_t block_size;   /* threads per block (64..256, multiple of 64); 0 = default 64 */
   int64_t max_steps;    /* attempt budget per trajectory      default 10^7 (< 2^32) */
-  int32_t lanes_per_wave; /* batched: active lanes per wave, 16/32/64; 0 = chosen from P */
+  int32_t lanes_per_wave; /* batched: active lanes per wave, 4/8/16/32/64; 0 = chosen from P */
   int32_t ssa_k;        /* batched: SSA steps per leap iteration, 1..64; 0 = default 4 */
   int32_t blocks_per_cu;/* batched: resident blocks per CU, 1..8; 0 = default 2 */
   uint32_t pid_stride;  /* row p uses RNG particle id pid_base + p * pid_stride;

@@ -356,9 +356,9 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
     return fail(LX_E_INVALID, "option out of range");
   if (o.block_size != 0 && (o.block_size < 64 || o.block_size > MAX_BLOCK || o.block_size % 64 != 0))
     return fail(LX_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
-  if (o.lanes_per_wave != 0 && o.lanes_per_wave != 16 && o.lanes_per_wave != 32 &&
-      o.lanes_per_wave != 64)
-    return fail(LX_E_INVALID, "lanes_per_wave must be 0, 16, 32 or 64");
+  if (o.lanes_per_wave != 0 && o.lanes_per_wave != 4 && o.lanes_per_wave != 8 &&
+      o.lanes_per_wave != 16 && o.lanes_per_wave != 32 && o.lanes_per_wave != 64)
+    return fail(LX_E_INVALID, "lanes_per_wave must be 0, 4, 8, 16, 32 or 64");
   if (o.ssa_k < 0 || o.ssa_k > 64) return fail(LX_E_INVALID, "ssa_k must be in [0, 64]");
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 8)
     return fail(LX_E_INVALID, "blocks_per_cu must be in [0, 8]");

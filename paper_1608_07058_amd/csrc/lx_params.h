@@ -25,7 +25,7 @@ struct SimParams {
   int n_c, n_ssa_ex, n_ssa_im, newton_maxit, kcap, mode, accumulate;
   // batched scheduler
   long long per_block;    // particles owned by each block (contiguous range)
-  int lanes;              // active lanes per wave (16, 32 or 64)
+  int lanes;              // active lanes per wave (4 to 64)
   int ssa_k;              // SSA steps a lane in an SSA burst takes per leap iteration
 };
 

@@ -105,7 +105,7 @@ def test_argument_validation_before_any_device_call():
         kw.update(bad)
         assert L.lx_simulate(net.handle, 0, None, None, kw["t_end"], kw["eps"], kw["mode"],
                              C.byref(o), None, None, None, None, None) == -1
-    for field, value in (("lambda_thr", 50.0), ("n_ssa_ex", 0), ("lanes_per_wave", 8),
+    for field, value in (("lambda_thr", 50.0), ("n_ssa_ex", 0), ("lanes_per_wave", 12),
                          ("ssa_k", 65), ("blocks_per_cu", 9), ("max_steps", 1 << 33),
                          ("block_size", 96), ("precision", 2)):
         ob = lx.options(**{field: value})

@@ -100,6 +100,8 @@ def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision, schedule
 
 
 @pytest.mark.parametrize("knobs", [
+    dict(lanes_per_wave=4, ssa_k=2, blocks_per_cu=1),
+    dict(lanes_per_wave=8, ssa_k=8, blocks_per_cu=2, block_size=64),
     dict(lanes_per_wave=16, ssa_k=1, blocks_per_cu=1),
     dict(lanes_per_wave=32, ssa_k=4, blocks_per_cu=1, block_size=64),
     dict(lanes_per_wave=64, ssa_k=16, blocks_per_cu=1, block_size=128),
@@ -242,7 +244,7 @@ def test_invalid_arguments_raise(lxm):
     with pytest.raises(lxm.LxError):
         lxm.simulate(h, th, xi, 1.0, block_size=100)
     with pytest.raises(lxm.LxError):
-        lxm.simulate(h, th, xi, 1.0, schedule="batched", lanes_per_wave=8)
+        lxm.simulate(h, th, xi, 1.0, schedule="batched", lanes_per_wave=12)
     with pytest.raises(lxm.LxError):
         lxm.simulate(h, th, xi, 1.0, schedule="batched", ssa_k=100)
 
