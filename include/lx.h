@@ -104,7 +104,10 @@ typedef struct lx_options {
   int32_t blocks_per_cu;/* batched: resident blocks per CU, 1..8; 0 = default 2 */
   uint32_t pid_stride;  /* row p uses RNG particle id pid_base + p * pid_stride;
                            0 means 1 (interleaved ids for sharding or mixed sets) */
-  int32_t reserved[6];
+  int32_t regroup;      /* batched: every `regroup` iterations the lanes of a block are
+                           regrouped by next action (SSA step or leap) so that waves are
+                           homogeneous; 0 = off, 1..64 */
+  int32_t reserved[5];
 } lx_options;
 
 /* Per-trajectory statistics (80 bytes). */

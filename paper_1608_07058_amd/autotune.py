@@ -27,6 +27,7 @@ GRID = {
     "ssa_k": (2, 4, 8, 16),
     "block_size": (64, 128, 256),
     "blocks_per_cu": (1, 2, 4),
+    "regroup": (0, 1, 2, 4),
 }
 
 

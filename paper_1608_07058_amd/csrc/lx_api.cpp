@@ -262,7 +262,7 @@ std::string set_source(const std::vector<const lx_network_s*>& nets, int precisi
          "  const long long blk = (long long)blockIdx.x - it.block_begin;\n"
          "  switch (k) {\n";
   for (size_t k = 0; k < nets.size(); ++k)
-    src << "    case " << k << ": lx::run_batched<LxNet" << k
+    src << "    case " << k << ": lx::run_sched<LxNet" << k
         << ">(blk, it.theta, it.x0, it.x_out, it.r_out, it.G_out, it.stats, q, &next); break;\n";
   src << "  }\n}\n";
   return src.str();
@@ -360,6 +360,7 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
       o.lanes_per_wave != 16 && o.lanes_per_wave != 32 && o.lanes_per_wave != 64)
     return fail(LX_E_INVALID, "lanes_per_wave must be 0, 4, 8, 16, 32 or 64");
   if (o.ssa_k < 0 || o.ssa_k > 64) return fail(LX_E_INVALID, "ssa_k must be in [0, 64]");
+  if (o.regroup < 0 || o.regroup > 64) return fail(LX_E_INVALID, "regroup must be in [0, 64]");
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 8)
     return fail(LX_E_INVALID, "blocks_per_cu must be in [0, 8]");
   {
@@ -425,6 +426,7 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
     L->prm.per_block = per_block;
     L->prm.lanes = lanes;
     L->prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
+    L->prm.regroup = o.regroup;
     L->grid = (P + per_block - 1) / per_block;
   }
   if (L->grid > 0x7fffffffLL) return fail(LX_E_INVALID, "P too large for one launch");
@@ -659,6 +661,7 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
   }
   if (begin > 0x7fffffffLL) return fail(LX_E_INVALID, "ensemble too large for one launch");
   prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
+  prm.regroup = o.regroup;
   hipFunction_t fn;
   st = get_kernel_src(items[0].net, key.str(), [&]() { return set_source(nets, o.precision, block); },
                       "lx_sim_set", &fn);

@@ -27,6 +27,7 @@ struct SimParams {
   long long per_block;    // particles owned by each block (contiguous range)
   int lanes;              // active lanes per wave (4 to 64)
   int ssa_k;              // SSA steps a lane in an SSA burst takes per leap iteration
+  int regroup;            // regroup lanes by next action every `regroup` iterations (0: never)
 };
 
 // Per-trajectory statistics (layout of the public lx_stats).

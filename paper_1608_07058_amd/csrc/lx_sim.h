@@ -85,7 +85,8 @@ struct Lane {
   R tau_p;
   int ssa_left;
   // counters
-  long long n_ssa, n_ex, n_im, n_rej, n_nit, n_nfail, n_clip;
+  u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip;  // < 2^32: attempts are bounded by max_steps
+  long long n_nit;
 
   __device__ __forceinline__ bool active(const SimParams& prm) const {
     return status == LANE_OK && t < prm.t_end;
@@ -143,6 +144,100 @@ struct Lane {
       s.attempts = e;
       stats[p] = s;
     }
+  }
+
+  // Number of 32-bit words of the state moved when lanes are regrouped.
+  static constexpr int STATE_WORDS = 20 + N + 3 * M;
+
+  // Write the trajectory's state to an LDS slot (regrouping).  theta, g, a
+  // and the plan's masks are not moved: they are reloaded or recomputed.
+  __device__ __forceinline__ void save(long long p, u32* w) const {
+    int q = 0;
+    w[q++] = (u32)p;
+    w[q++] = (u32)((unsigned long long)p >> 32);
+    w[q++] = pid;
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[q++] = (u32)x[i];
+#pragma unroll
+    for (int j = 0; j < M; ++j) w[q++] = (u32)r[j];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const unsigned long long b = __builtin_bit_cast(unsigned long long, G[j]);
+      w[q++] = (u32)b;
+      w[q++] = (u32)(b >> 32);
+    }
+    const unsigned long long tb = __builtin_bit_cast(unsigned long long, t);
+    w[q++] = (u32)tb;
+    w[q++] = (u32)(tb >> 32);
+    w[q++] = e;
+    w[q++] = (u32)status;
+    w[q++] = (plan ? 1u : 0u) | (implicit ? 2u : 0u);
+    const double tp = (double)tau_p;
+    const unsigned long long pb = __builtin_bit_cast(unsigned long long, tp);
+    w[q++] = (u32)pb;
+    w[q++] = (u32)(pb >> 32);
+    w[q++] = (u32)ssa_left;
+    w[q++] = n_ssa;
+    w[q++] = n_ex;
+    w[q++] = n_im;
+    w[q++] = n_rej;
+    w[q++] = n_nfail;
+    w[q++] = n_clip;
+    w[q++] = (u32)n_nit;
+    w[q++] = (u32)((unsigned long long)n_nit >> 32);
+  }
+
+  // Read a state written by save(); theta is reloaded from the input, the
+  // propensities (and, for a lane retrying a leap, its plan's critical set)
+  // are recomputed from the state, which reproduces them exactly.
+  __device__ __forceinline__ long long restore(const u32* w, const double* __restrict__ theta,
+                                               const SimParams& prm) {
+    int q = 0;
+    const long long p = (long long)((unsigned long long)w[0] | ((unsigned long long)w[1] << 32));
+    q = 2;
+    pid = w[q++];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = (int)w[q++];
+#pragma unroll
+    for (int j = 0; j < M; ++j) r[j] = (int)w[q++];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const unsigned long long b = (unsigned long long)w[q] | ((unsigned long long)w[q + 1] << 32);
+      q += 2;
+      G[j] = __builtin_bit_cast(double, b);
+    }
+    const unsigned long long tb = (unsigned long long)w[q] | ((unsigned long long)w[q + 1] << 32);
+    q += 2;
+    t = __builtin_bit_cast(double, tb);
+    e = w[q++];
+    status = (int)w[q++];
+    const u32 flags = w[q++];
+    const unsigned long long pb = (unsigned long long)w[q] | ((unsigned long long)w[q + 1] << 32);
+    q += 2;
+    const double tp = __builtin_bit_cast(double, pb);
+    ssa_left = (int)w[q++];
+    n_ssa = w[q++];
+    n_ex = w[q++];
+    n_im = w[q++];
+    n_rej = w[q++];
+    n_nfail = w[q++];
+    n_clip = w[q++];
+    n_nit = (long long)((unsigned long long)w[q] | ((unsigned long long)w[q + 1] << 32));
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      th[j] = theta[p * M + j];
+      thr[j] = (R)th[j];
+    }
+    gvalid = false;
+    plan = false;
+    implicit = false;
+    if (flags & 1u) {  // retrying a leap: rebuild the plan, keep the halved tau'
+      propensities();
+      make_plan(prm);
+      implicit = (flags & 2u) != 0;
+      tau_p = (R)tp;
+    }
+    return p;
   }
 
   // a_j = theta_j g_j (Background section); a0 summed in ascending j.
@@ -690,6 +785,95 @@ __device__ __forceinline__ void run_batched(long long blk, const double* __restr
   }
 }
 
+// Batched form with regrouping by next action.  Every `regroup` iterations
+// the lanes of the block write their state to LDS in the order (lanes whose
+// next action is an SSA step, lanes that plan or leap, empty lanes) and read
+// back the state of their new position, so that waves hold one kind of lane.
+// A wave that still holds both kinds (the boundary wave) lets one kind act per
+// iteration, alternating, so every lane acts at least every second iteration
+// and no wave pays for both paths.  Refill from the block's range as in
+// run_batched.  Each trajectory's actions, and hence every result, are
+// unchanged.
+template <class NET>
+__device__ __forceinline__ void run_regroup(long long blk, const double* __restrict__ theta,
+                                            const int* __restrict__ x0, int* x_out, int* r_out,
+                                            double* G_out, Stats* stats, const SimParams& prm,
+                                            unsigned long long* next) {
+  typedef Lane<LX_POLICY, NET> LaneT;
+  constexpr int STRIDE = LaneT::STATE_WORDS;
+  __shared__ u32 slots[LX_BLOCK * STRIDE];
+  __shared__ int counts[2 * (LX_BLOCK / 64)];
+  const int lane_id = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const bool slot_thread = lane_id < prm.lanes;
+  const int vslot = wave * prm.lanes + lane_id;
+  const long long lo = blk * prm.per_block;
+  long long hi = lo + prm.per_block;
+  if (hi > prm.P) hi = prm.P;
+  if (threadIdx.x == 0) *next = (unsigned long long)(lo + (long long)waves * prm.lanes);
+  __syncthreads();
+  const Key key{prm.k0, prm.k1};
+  long long p = lo + vslot;
+  bool has = slot_thread && p < hi;
+  LaneT lane;
+  if (has) lane.load(p, theta, x0, r_out, G_out, prm);
+  for (int iter = 0;; ++iter) {
+    while (has && !lane.active(prm)) {  // store finished trajectories, refill
+      lane.store(p, x_out, r_out, G_out, stats);
+      p = (long long)atomicAdd(next, 1ull);
+      has = p < hi;
+      if (has) lane.load(p, theta, x0, r_out, G_out, prm);
+    }
+    if (!__syncthreads_or(has ? 1 : 0)) break;
+    int cls = has ? (lane.in_ssa(prm) ? 0 : 1) : 2;
+    if (prm.regroup > 0 && iter % prm.regroup == 0) {
+      const unsigned long long b0 = __ballot(cls == 0);
+      const unsigned long long b1 = __ballot(cls == 1);
+      if (lane_id == 0) {
+        counts[2 * wave] = __popcll(b0);
+        counts[2 * wave + 1] = __popcll(b1);
+      }
+      __syncthreads();
+      int n0 = 0, n1 = 0, before0 = 0, before1 = 0;
+      for (int w = 0; w < waves; ++w) {
+        if (w < wave) {
+          before0 += counts[2 * w];
+          before1 += counts[2 * w + 1];
+        }
+        n0 += counts[2 * w];
+        n1 += counts[2 * w + 1];
+      }
+      const unsigned long long below = (1ull << lane_id) - 1ull;
+      if (cls == 0) lane.save(p, slots + (before0 + __popcll(b0 & below)) * STRIDE);
+      if (cls == 1) lane.save(p, slots + (n0 + before1 + __popcll(b1 & below)) * STRIDE);
+      __syncthreads();
+      has = slot_thread && vslot < n0 + n1;
+      if (has) p = lane.restore(slots + vslot * STRIDE, theta, prm);
+      cls = has ? (lane.in_ssa(prm) ? 0 : 1) : 2;
+    }
+    const bool any0 = __ballot(cls == 0) != 0ull;
+    const bool any1 = __ballot(cls == 1) != 0ull;
+    const bool run_ssa = any0 && (!any1 || (iter & 1) == 0);
+    if (cls == 0 && run_ssa) {
+      for (int k = 0; k < prm.ssa_k; ++k) {
+        if (!(lane.active(prm) && lane.in_ssa(prm))) break;
+        lane.ssa_only(prm, key);
+      }
+    } else if (cls == 1 && !run_ssa) {
+      lane.step(prm, key);
+    }
+  }
+}
+
+template <class NET>
+__device__ __forceinline__ void run_sched(long long blk, const double* __restrict__ theta,
+                                          const int* __restrict__ x0, int* x_out, int* r_out,
+                                          double* G_out, Stats* stats, const SimParams& prm,
+                                          unsigned long long* next) {
+  if (prm.regroup > 0) run_regroup<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next);
+  else run_batched<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next);
+}
 }  // namespace lx
 #endif
 
@@ -698,7 +882,7 @@ extern "C" __global__ void __launch_bounds__(LX_BLOCK)
     lx_sim_batched(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
                    int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
   __shared__ unsigned long long next;
-  lx::run_batched<LxNet>(blockIdx.x, theta, x0, x_out, r_out, G_out, stats, prm, &next);
+  lx::run_sched<LxNet>(blockIdx.x, theta, x0, x_out, r_out, G_out, stats, prm, &next);
 }
 #endif
 

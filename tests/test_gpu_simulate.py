@@ -86,14 +86,15 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("schedule", ["plain", "batched"])
+@pytest.mark.parametrize("schedule", ["plain", "batched", "regroup"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision, schedule):
     name, net, mode, t_end, P = case
     theta = W.gamma_prior_theta(net, P, seed=7)
     _, x0 = W.tile(net, P)
-    got = gpu_run(lxm, net, theta, x0, t_end, mode, precision=precision, schedule=schedule)
+    kw = dict(schedule="batched", regroup=1) if schedule == "regroup" else dict(schedule=schedule)
+    got = gpu_run(lxm, net, theta, x0, t_end, mode, precision=precision, **kw)
     ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode=mode, precision=precision)
     assert_same(got, ref, f"{name}/{precision}/{schedule}")
     assert np.all(got["stats"]["status"] == 0)
@@ -106,6 +107,9 @@ def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision, schedule
     dict(lanes_per_wave=32, ssa_k=4, blocks_per_cu=1, block_size=64),
     dict(lanes_per_wave=64, ssa_k=16, blocks_per_cu=1, block_size=128),
     dict(lanes_per_wave=64, ssa_k=64, blocks_per_cu=8),
+    dict(lanes_per_wave=16, ssa_k=8, blocks_per_cu=1, regroup=1),
+    dict(lanes_per_wave=64, ssa_k=4, blocks_per_cu=2, regroup=3),
+    dict(lanes_per_wave=8, ssa_k=2, blocks_per_cu=1, block_size=128, regroup=2),
 ])
 def test_batched_refill_and_knobs(lxm, orc, knobs):
     # Few resident blocks force every lane to refill from its block's range
@@ -247,6 +251,8 @@ def test_invalid_arguments_raise(lxm):
         lxm.simulate(h, th, xi, 1.0, schedule="batched", lanes_per_wave=12)
     with pytest.raises(lxm.LxError):
         lxm.simulate(h, th, xi, 1.0, schedule="batched", ssa_k=100)
+    with pytest.raises(lxm.LxError):
+        lxm.simulate(h, th, xi, 1.0, schedule="batched", regroup=-1)
 
 
 # ---------------------------------------------------------------------------
@@ -353,7 +359,9 @@ def _set_run(lxm, wl, precision, **opts):
 def test_set_matches_oracle(lxm, orc, precision):
     wl = W.mixed_set_workload(P=12000)
     got = _set_run(lxm, wl, precision)
+    regrouped = _set_run(lxm, wl, precision, regroup=1, lanes_per_wave=16)
     for k, net in enumerate(wl.nets):
+        assert_same(regrouped[k], got[k], f"{net.name} regrouped")
         ref = orc.simulate(net.m, net.p, wl.theta[k], wl.x0[k], wl.t_end, mode=wl.mode,
                            precision=precision, pid_base=k, pid_stride=3)
         assert_same(got[k], ref, f"{net.name}/{precision}")
