@@ -106,8 +106,12 @@ typedef struct lx_options {
                            0 means 1 (interleaved ids for sharding or mixed sets) */
   int32_t regroup;      /* batched: every `regroup` iterations the lanes of a block are
                            regrouped by next action (SSA step or leap) so that waves are
-                           homogeneous; 0 = off, 1..64 */
-  int32_t reserved[5];
+                           homogeneous; 0 = off, 1..64 (one lane per trajectory only) */
+  int32_t lanes_per_traj; /* batched: lanes per trajectory, 1, 2, 4, 8 or 16 (0 = 1); the lanes of a
+                           trajectory split its Poisson draws and upcoming SSA draws;
+                           lanes_per_wave counts lanes, so a wave holds
+                           lanes_per_wave / lanes_per_traj trajectories */
+  int32_t reserved[4];
 } lx_options;
 
 /* Per-trajectory statistics (80 bytes). */

@@ -23,12 +23,22 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_FILE = os.path.join(HERE, "tuned.json")
 
 GRID = {
-    "lanes_per_wave": (4, 8, 16, 32, 64),
-    "ssa_k": (2, 4, 8, 16),
-    "block_size": (64, 128, 256),
-    "blocks_per_cu": (1, 2, 4),
-    "regroup": (0, 1, 2, 4),
+    "lanes_per_traj": (1, 4, 8, 16),
+    "lanes_per_wave": (16, 32, 64),
+    "ssa_k": (4, 8, 16),
+    "block_size": (64, 256),
+    "blocks_per_cu": (2, 4, 8),
+    "regroup": (0, 2),
 }
+
+
+def valid(opts, P):
+    tpl = opts.get("lanes_per_traj", 1)
+    if tpl > 1 and opts.get("regroup", 0):
+        return False
+    if opts["lanes_per_wave"] < tpl:
+        return False
+    return (opts["lanes_per_wave"] // tpl) * (opts["block_size"] // 64) <= P
 
 
 def key_of(net_m, net_p, P, precision, mode, arch="gfx950"):
@@ -66,7 +76,7 @@ def tune(lx, h, theta, x0, t_end, eps, mode, precision, grid=None, reps=2, log=N
     table = []
     for values in itertools.product(*(grid[n] for n in names)):
         opts = dict(zip(names, values))
-        if opts["lanes_per_wave"] * (opts["block_size"] // 64) > P:
+        if not valid(opts, P):
             continue
         kw = dict(schedule="batched", precision=precision, **opts)
         lx.simulate(h, theta, x0, t_end, eps, mode, out=out, stream=stream, **kw)  # warm-up

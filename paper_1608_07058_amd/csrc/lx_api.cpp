@@ -228,9 +228,11 @@ std::string named_net(const lx_network_s& n, int k) {
 }
 
 // Full hipRTC source of one kernel variant of a network.
-std::string kernel_source(const lx_network_s& net, const char* variant, int precision, int block) {
+std::string kernel_source(const lx_network_s& net, const char* variant, int precision, int block,
+                          int tpl) {
   std::ostringstream src;
   src << "// generated by liblx\n";
+  src << "#define LX_TPL " << tpl << "\n";
   src << "#define LX_POLICY " << (precision == LX_PREC_MIXED ? "lx::Mixed" : "lx::F64") << "\n";
   src << "#define LX_BLOCK " << block << "\n";
   if (strcmp(variant, "hooks") == 0) src << "#define LX_HOOKS 1\n";
@@ -242,9 +244,11 @@ std::string kernel_source(const lx_network_s& net, const char* variant, int prec
 
 // hipRTC source of the multi-network kernel: every network of the set as
 // LxNet<k>, and a kernel that picks the network of its block.
-std::string set_source(const std::vector<const lx_network_s*>& nets, int precision, int block) {
+std::string set_source(const std::vector<const lx_network_s*>& nets, int precision, int block,
+                       int tpl) {
   std::ostringstream src;
   src << "// generated by liblx (network set)\n";
+  src << "#define LX_TPL " << tpl << "\n";
   src << "#define LX_POLICY " << (precision == LX_PREC_MIXED ? "lx::Mixed" : "lx::F64") << "\n";
   src << "#define LX_BLOCK " << block << "\n#define LX_SET 1\n";
   src << lx_src_params << "\n" << lx_src_device << "\n";
@@ -316,11 +320,12 @@ lx_status get_kernel_src(lx_network_s* owner, const std::string& variant_key, F 
 }
 
 lx_status get_kernel(lx_network_s* net, const char* variant, int precision, int block,
-                     const char* fname, hipFunction_t* fn) {
+                     const char* fname, hipFunction_t* fn, int tpl = 1) {
   std::ostringstream key;
-  key << variant << "/" << precision << "/" << block;
+  key << variant << "/" << precision << "/" << block << "/tpl" << tpl;
   return get_kernel_src(net, key.str(),
-                        [&]() { return kernel_source(*net, variant, precision, block); }, fname, fn);
+                        [&]() { return kernel_source(*net, variant, precision, block, tpl); },
+                        fname, fn);
 }
 
 // Active lanes per wave of the batched schedule: full waves when the ensemble
@@ -330,6 +335,15 @@ int choose_lanes(int requested, long long P, int cus) {
   if (requested) return requested;
   const long long simds = 4LL * cus;
   return P >= 64 * simds ? 64 : (P >= 32 * simds ? 32 : 16);
+}
+
+int tpl_of(const lx_options& o) { return o.lanes_per_traj > 1 ? o.lanes_per_traj : 1; }
+
+// Trajectories per wave of the batched schedule.
+int traj_per_wave(const lx_options& o, long long P, int cus) {
+  const int tpl = tpl_of(o);
+  if (tpl > 1) return (o.lanes_per_wave ? o.lanes_per_wave : 64) / tpl;
+  return choose_lanes(o.lanes_per_wave, P, cus);
 }
 
 lx_status device_cus(int* cus) {
@@ -361,6 +375,13 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
     return fail(LX_E_INVALID, "lanes_per_wave must be 0, 4, 8, 16, 32 or 64");
   if (o.ssa_k < 0 || o.ssa_k > 64) return fail(LX_E_INVALID, "ssa_k must be in [0, 64]");
   if (o.regroup < 0 || o.regroup > 64) return fail(LX_E_INVALID, "regroup must be in [0, 64]");
+  if (o.lanes_per_traj < 0 || o.lanes_per_traj > 16 ||
+      (o.lanes_per_traj & (o.lanes_per_traj - 1)) != 0)
+    return fail(LX_E_INVALID, "lanes_per_traj must be 0, 1, 2, 4, 8 or 16");
+  if (o.lanes_per_traj > 1 && o.regroup > 0)
+    return fail(LX_E_INVALID, "regroup needs one lane per trajectory");
+  if (o.lanes_per_traj > 1 && o.lanes_per_wave != 0 && o.lanes_per_wave < o.lanes_per_traj)
+    return fail(LX_E_INVALID, "lanes_per_wave must be at least lanes_per_traj");
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 8)
     return fail(LX_E_INVALID, "blocks_per_cu must be in [0, 8]");
   {
@@ -411,14 +432,15 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
   L->batched = o.schedule == LX_SCHED_BATCHED;
   L->block = o.block_size ? o.block_size : (L->batched ? 256 : 64);
   st = get_kernel(net, L->batched ? "batched" : "plain", o.precision, L->block,
-                  L->batched ? "lx_sim_batched" : "lx_sim_plain", &L->fn);
+                  L->batched ? "lx_sim_batched" : "lx_sim_plain", &L->fn,
+                  L->batched ? tpl_of(o) : 1);
   if (st != LX_OK) return st;
   L->grid = (P + L->block - 1) / L->block;
   if (L->batched) {
     int cus = 0;
     st = device_cus(&cus);
     if (st != LX_OK) return st;
-    const int lanes = choose_lanes(o.lanes_per_wave, P, cus);
+    const int lanes = traj_per_wave(o, P, cus);
     const long long round = (long long)(L->block / 64) * lanes;
     const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
     long long per_block = (P + max_grid - 1) / max_grid;
@@ -560,7 +582,7 @@ lx_status lx_network_prepare(lx_network net, int32_t precision, int32_t schedule
   const int block = block_size ? block_size : (schedule == LX_SCHED_BATCHED ? 256 : 64);
   std::vector<char> code;
   return compile_source(
-      kernel_source(*net, schedule == LX_SCHED_BATCHED ? "batched" : "plain", precision, block),
+      kernel_source(*net, schedule == LX_SCHED_BATCHED ? "batched" : "plain", precision, block, 1),
       &code);
 }
 
@@ -627,7 +649,7 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
   int cus = 0;
   st = device_cus(&cus);
   if (st != LX_OK) return st;
-  const int lanes = choose_lanes(o.lanes_per_wave, total, cus);
+  const int lanes = traj_per_wave(o, total, cus);
   const long long round = (long long)(block / 64) * lanes;
   const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
   long long per_block = (total + max_grid - 1) / max_grid;
@@ -638,7 +660,7 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
   long long begin = 0;
   std::vector<const lx_network_s*> nets;
   std::ostringstream key;
-  key << "set/" << o.precision << "/" << block;
+  key << "set/" << o.precision << "/" << block << "/tpl" << tpl_of(o);
   for (int k = 0; k < K; ++k) {
     const lx_set_item& it = items[k];
     lx::SetItem& d = args.it[k];
@@ -663,7 +685,8 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
   prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
   prm.regroup = o.regroup;
   hipFunction_t fn;
-  st = get_kernel_src(items[0].net, key.str(), [&]() { return set_source(nets, o.precision, block); },
+  st = get_kernel_src(items[0].net, key.str(),
+                      [&]() { return set_source(nets, o.precision, block, tpl_of(o)); },
                       "lx_sim_set", &fn);
   if (st != LX_OK) return st;
   void* kargs[] = {(void*)&args, (void*)&prm};
@@ -748,7 +771,7 @@ lx_status lx_test_tau_select(lx_network net, int64_t Q, const double* theta, con
   if (!theta || !x || !a || !crit || !eq || !tau || !action)
     return fail(LX_E_INVALID, "null pointer");
   hipFunction_t fn;
-  st = get_kernel(net, "hooks", o.precision, 64, "lx_hook_tau", &fn);
+  st = get_kernel(net, "hooks", o.precision, 64, "lx_hook_tau", &fn, 1);
   if (st != LX_OK) return st;
   void* args[] = {(void*)&theta, (void*)&x, (void*)&a, (void*)&crit, (void*)&eq,
                   (void*)&tau, (void*)&action, (void*)&prm};
@@ -772,7 +795,7 @@ lx_status lx_test_implicit(lx_network net, int64_t Q, const double* theta, const
   if (!theta || !x || !tau || !Pj || !jc || !k || !ok || !iters)
     return fail(LX_E_INVALID, "null pointer");
   hipFunction_t fn;
-  st = get_kernel(net, "hooks", LX_PREC_FP64, 64, "lx_hook_implicit", &fn);
+  st = get_kernel(net, "hooks", LX_PREC_FP64, 64, "lx_hook_implicit", &fn, 1);
   if (st != LX_OK) return st;
   void* args[] = {(void*)&theta, (void*)&x, (void*)&tau, (void*)&Pj, (void*)&jc,
                   (void*)&k, (void*)&ok, (void*)&iters, (void*)&prm};

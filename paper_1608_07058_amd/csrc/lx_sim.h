@@ -59,7 +59,18 @@ __device__ __forceinline__ double dg_of(int j, int k, const double (&y)[NET::N])
   return gj;
 }
 
-template <class P, class NET>
+// Cross-lane read within groups of TPL lanes (lane s of the caller's group).
+template <int TPL, class T>
+__device__ __forceinline__ T group_read(T v, int s) {
+  return __shfl(v, s, TPL);
+}
+
+// Lane state of one trajectory.  With TPL > 1 a trajectory occupies TPL lanes
+// that hold identical state and run identical control flow; they split the
+// Poisson draws of a leap (one reaction each) and the draws of upcoming SSA
+// steps (one attempt each) and exchange the results, so every value is the
+// one the single-lane form computes.
+template <class P, class NET, int TPL = 1>
 struct Lane {
   typedef typename P::R R;
   static constexpr int N = NET::N;
@@ -369,11 +380,17 @@ struct Lane {
   // One SSA step (Gillespie 1977 direct method) with exact G.
   __device__ __forceinline__ void ssa_step(const SimParams& prm, const Key& key) {
     const Words4 w = draw_block(key, pid, e, SITE_SSA, 0);
-    e = e + 1;
-    n_ssa += 1;
     R u1, u2;
     P::uniforms(w, &u1, &u2);
-    const double tau_s = (double)(-P::ulog(u1) / a0);
+    ssa_apply(prm, -P::ulog(u1), u2);
+  }
+
+  // The SSA step given its draws: E = -log(u1) of the step's first uniform and
+  // the second uniform u2.
+  __device__ __forceinline__ void ssa_apply(const SimParams& prm, R E, R u2) {
+    e = e + 1;
+    n_ssa += 1;
+    const double tau_s = (double)(E / a0);
     const double rem = prm.t_end - t;
     if (tau_s >= rem) {
       absorb(prm);
@@ -599,13 +616,43 @@ struct Lane {
     const R lam_thr = (R)prm.lam_thr;
     long long k[M];
     bool overflow = false;
+    if constexpr (TPL == 1) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      k[j] = 0;
-      if ((ncr >> j) & 1u) {
-        const long long kj = poisson_sample<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
-        overflow = overflow || kj < 0;
-        k[j] = kj;
+      for (int j = 0; j < M; ++j) {
+        k[j] = 0;
+        if ((ncr >> j) & 1u) {
+          const long long kj =
+              poisson_sample<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
+          overflow = overflow || kj < 0;
+          k[j] = kj;
+        }
+      }
+    } else {
+      // lane `sub` of the group draws reaction g*TPL + sub of each group g
+      const int sub = (int)(threadIdx.x & (TPL - 1));
+#pragma unroll
+      for (int g = 0; g < (M + TPL - 1) / TPL; ++g) {
+        R aj = (R)0;
+        bool nc = false;
+#pragma unroll
+        for (int q = 0; q < TPL; ++q) {
+          if (g * TPL + q < M && sub == q) {
+            aj = a[g * TPL + q];
+            nc = ((ncr >> (g * TPL + q)) & 1u) != 0;
+          }
+        }
+        long long kj = 0;
+        if (nc)
+          kj = poisson_sample<P>(aj * tau_rr, lam_thr, prm.kcap, key, pid, ea,
+                                 (u32)(g * TPL + sub));
+#pragma unroll
+        for (int q = 0; q < TPL; ++q) {
+          if (g * TPL + q < M) {
+            const long long v = group_read<TPL>(kj, q);
+            k[g * TPL + q] = v;
+            overflow = overflow || v < 0;
+          }
+        }
       }
     }
     if (overflow) {
@@ -711,6 +758,45 @@ struct Lane {
     if (ssa_left > 0) ssa_left -= 1;
     plan = false;
   }
+
+  // Up to kmax SSA steps while the lane stays in an SSA burst.  With TPL > 1
+  // the draws of the next TPL attempts are made in parallel (lane s of the
+  // group draws attempt e + s) and applied in order.
+  __device__ __forceinline__ void ssa_burst(const SimParams& prm, const Key& key, int kmax) {
+    if constexpr (TPL == 1) {
+      for (int k = 0; k < kmax; ++k) {
+        if (!(active(prm) && in_ssa(prm))) break;
+        ssa_only(prm, key);
+      }
+    } else {
+      const u32 sub = threadIdx.x & (TPL - 1);
+      int done = 0;
+      while (done < kmax && active(prm) && in_ssa(prm)) {
+        const Words4 w = draw_block(key, pid, e + sub, SITE_SSA, 0);
+        R u1, u2;
+        P::uniforms(w, &u1, &u2);
+        const R E = -P::ulog(u1);
+#pragma unroll
+        for (int s = 0; s < TPL; ++s) {
+          const R Es = group_read<TPL>(E, s);
+          const R u2s = group_read<TPL>(u2, s);
+          if (done < kmax && active(prm) && in_ssa(prm)) {
+            propensities();
+            if (a0 == (R)0) {
+              absorb(prm);
+            } else if ((long long)e >= prm.max_steps) {
+              status = LANE_STEP_BUDGET;
+            } else {
+              ssa_apply(prm, Es, u2s);
+              if (ssa_left > 0) ssa_left -= 1;
+              plan = false;
+            }
+            ++done;
+          }
+        }
+      }
+    }
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -721,6 +807,9 @@ struct Lane {
 #endif
 #ifndef LX_BLOCK
 #define LX_BLOCK 64
+#endif
+#ifndef LX_TPL
+#define LX_TPL 1
 #endif
 
 }  // namespace lx
@@ -755,7 +844,10 @@ __device__ __forceinline__ void run_batched(long long blk, const double* __restr
                                             const int* __restrict__ x0, int* x_out, int* r_out,
                                             double* G_out, Stats* stats, const SimParams& prm,
                                             unsigned long long* next) {
+  constexpr int TPL = LX_TPL;
   const int lane_id = threadIdx.x & 63;
+  const int slot = lane_id / TPL;  // trajectory slot of this lane in its wave
+  const int sub = lane_id & (TPL - 1);
   const int wave = threadIdx.x >> 6;
   const int waves = blockDim.x >> 6;
   const long long lo = blk * prm.per_block;
@@ -764,21 +856,20 @@ __device__ __forceinline__ void run_batched(long long blk, const double* __restr
   if (threadIdx.x == 0) *next = (unsigned long long)(lo + (long long)waves * prm.lanes);
   __syncthreads();
   const Key key{prm.k0, prm.k1};
-  long long p = lo + (long long)wave * prm.lanes + lane_id;
-  bool has = lane_id < prm.lanes && p < hi;
-  Lane<LX_POLICY, NET> lane;
+  long long p = lo + (long long)wave * prm.lanes + slot;
+  bool has = slot < prm.lanes && p < hi;
+  Lane<LX_POLICY, NET, TPL> lane;
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
   while (has) {
     if (lane.active(prm)) {
-      for (int k = 0; k < prm.ssa_k; ++k) {
-        if (!(lane.active(prm) && lane.in_ssa(prm))) break;
-        lane.ssa_only(prm, key);
-      }
+      lane.ssa_burst(prm, key, prm.ssa_k);
       if (lane.active(prm) && !lane.in_ssa(prm)) lane.step(prm, key);
     }
     if (!lane.active(prm)) {
-      lane.store(p, x_out, r_out, G_out, stats);
-      p = (long long)atomicAdd(next, 1ull);
+      if (sub == 0) lane.store(p, x_out, r_out, G_out, stats);
+      long long pn = 0;
+      if (sub == 0) pn = (long long)atomicAdd(next, 1ull);
+      p = group_read<TPL>(pn, 0);
       has = p < hi;
       if (has) lane.load(p, theta, x0, r_out, G_out, prm);
     }
@@ -871,7 +962,8 @@ __device__ __forceinline__ void run_sched(long long blk, const double* __restric
                                           const int* __restrict__ x0, int* x_out, int* r_out,
                                           double* G_out, Stats* stats, const SimParams& prm,
                                           unsigned long long* next) {
-  if (prm.regroup > 0) run_regroup<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next);
+  if (LX_TPL == 1 && prm.regroup > 0)
+    run_regroup<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next);
   else run_batched<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next);
 }
 }  // namespace lx

@@ -107,7 +107,7 @@ def test_argument_validation_before_any_device_call():
                              C.byref(o), None, None, None, None, None) == -1
     for field, value in (("lambda_thr", 50.0), ("n_ssa_ex", 0), ("lanes_per_wave", 12),
                          ("ssa_k", 65), ("blocks_per_cu", 9), ("max_steps", 1 << 33),
-                         ("block_size", 96), ("precision", 2), ("regroup", 65)):
+                         ("block_size", 96), ("precision", 2), ("regroup", 65), ("lanes_per_traj", 3), ("lanes_per_traj", 32)):
         ob = lx.options(**{field: value})
         assert L.lx_simulate(net.handle, 0, None, None, 1.0, 0.03, 0, C.byref(ob), None, None,
                              None, None, None) == -1, field

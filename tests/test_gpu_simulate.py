@@ -86,14 +86,15 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("schedule", ["plain", "batched", "regroup"])
+@pytest.mark.parametrize("schedule", ["plain", "batched", "regroup", "group4"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision, schedule):
     name, net, mode, t_end, P = case
     theta = W.gamma_prior_theta(net, P, seed=7)
     _, x0 = W.tile(net, P)
-    kw = dict(schedule="batched", regroup=1) if schedule == "regroup" else dict(schedule=schedule)
+    kw = {"regroup": dict(schedule="batched", regroup=1),
+          "group4": dict(schedule="batched", lanes_per_traj=4)}.get(schedule, dict(schedule=schedule))
     got = gpu_run(lxm, net, theta, x0, t_end, mode, precision=precision, **kw)
     ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode=mode, precision=precision)
     assert_same(got, ref, f"{name}/{precision}/{schedule}")
@@ -110,6 +111,11 @@ def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision, schedule
     dict(lanes_per_wave=16, ssa_k=8, blocks_per_cu=1, regroup=1),
     dict(lanes_per_wave=64, ssa_k=4, blocks_per_cu=2, regroup=3),
     dict(lanes_per_wave=8, ssa_k=2, blocks_per_cu=1, block_size=128, regroup=2),
+    dict(lanes_per_wave=64, lanes_per_traj=4, ssa_k=8, blocks_per_cu=1),
+    dict(lanes_per_wave=32, lanes_per_traj=2, ssa_k=5, blocks_per_cu=2, block_size=64),
+    dict(lanes_per_wave=8, lanes_per_traj=4, ssa_k=3, blocks_per_cu=1, block_size=128),
+    dict(lanes_per_wave=64, lanes_per_traj=8, ssa_k=8, blocks_per_cu=8),
+    dict(lanes_per_wave=64, lanes_per_traj=16, ssa_k=20, blocks_per_cu=4, block_size=256),
 ])
 def test_batched_refill_and_knobs(lxm, orc, knobs):
     # Few resident blocks force every lane to refill from its block's range
@@ -124,7 +130,7 @@ def test_batched_refill_and_knobs(lxm, orc, knobs):
     assert_same(got, ref, str(knobs))
 
 
-@pytest.mark.parametrize("schedule", ["plain", "batched"])
+@pytest.mark.parametrize("schedule", ["plain", "batched", "tuned"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_full_size_dimer_sampled(lxm, orc, precision, schedule):
     # The benchmark workload (16384 trajectories, in the launch configuration
@@ -132,8 +138,11 @@ def test_full_size_dimer_sampled(lxm, orc, precision, schedule):
     # recomputed by the oracle.
     wl = W.dimer_workload()
     net, theta, x0 = wl.nets[0], wl.theta[0], wl.x0[0]
-    got = gpu_run(lxm, net, theta, x0, wl.t_end, wl.mode, precision=precision,
-                  schedule=schedule)
+    kw = dict(schedule=schedule)
+    if schedule == "tuned":  # the knobs the benchmark uses
+        from paper_1608_07058_amd import autotune
+        kw = dict(schedule="batched", **autotune.lookup(net.m, net.p, wl.P, precision, wl.mode))
+    got = gpu_run(lxm, net, theta, x0, wl.t_end, wl.mode, precision=precision, **kw)
     rng = np.random.default_rng(5)
     sample = np.concatenate([[0, 63, 64, wl.P - 1], rng.choice(wl.P, 60, replace=False)])
     for p in sample:
@@ -253,6 +262,10 @@ def test_invalid_arguments_raise(lxm):
         lxm.simulate(h, th, xi, 1.0, schedule="batched", ssa_k=100)
     with pytest.raises(lxm.LxError):
         lxm.simulate(h, th, xi, 1.0, schedule="batched", regroup=-1)
+    with pytest.raises(lxm.LxError):
+        lxm.simulate(h, th, xi, 1.0, schedule="batched", lanes_per_traj=3)
+    with pytest.raises(lxm.LxError):
+        lxm.simulate(h, th, xi, 1.0, schedule="batched", lanes_per_traj=2, regroup=1)
 
 
 # ---------------------------------------------------------------------------
@@ -360,8 +373,10 @@ def test_set_matches_oracle(lxm, orc, precision):
     wl = W.mixed_set_workload(P=12000)
     got = _set_run(lxm, wl, precision)
     regrouped = _set_run(lxm, wl, precision, regroup=1, lanes_per_wave=16)
+    grouped = _set_run(lxm, wl, precision, lanes_per_traj=2)
     for k, net in enumerate(wl.nets):
         assert_same(regrouped[k], got[k], f"{net.name} regrouped")
+        assert_same(grouped[k], got[k], f"{net.name} lane groups")
         ref = orc.simulate(net.m, net.p, wl.theta[k], wl.x0[k], wl.t_end, mode=wl.mode,
                            precision=precision, pid_base=k, pid_stride=3)
         assert_same(got[k], ref, f"{net.name}/{precision}")
