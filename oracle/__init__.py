@@ -86,6 +86,7 @@ def lib():
         L.orc_poisson.argtypes = [C.c_int64, P, P, P, P, C.c_uint64, C.c_uint32, C.c_double,
                                   C.c_int32, P]
         L.orc_exponential.argtypes = [C.c_int64, P, P, C.c_uint64, C.c_uint32, C.c_int32, P]
+        L.orc_ptrs_log_density.argtypes = [C.c_int64, P, P, C.c_int32, P, P]
         L.orc_tau_select.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int64, P, P,
                                      C.POINTER(Options), P, P, P, P, P]
         L.orc_tau_select.restype = C.c_int
@@ -206,6 +207,18 @@ def poisson(lam, pid, e, site, *, seed=160807058, stream=0, lambda_thr=10.0, pre
     lib().orc_poisson(n, _ptr(lam), _ptr(pid), _ptr(e), _ptr(site), seed, stream,
                       float(lambda_thr), PRECISIONS.get(precision, precision), _ptr(out))
     return out
+
+
+def ptrs_log_density(k, lam, *, precision="fp64"):
+    """(factor, rhs) of the PTRS acceptance test: log p(k; lam) = rhs - log(factor)."""
+    k, lam = np.broadcast_arrays(np.asarray(k, np.float64), np.asarray(lam, np.float64))
+    k = np.ascontiguousarray(k).reshape(-1)
+    lam = np.ascontiguousarray(lam).reshape(-1)
+    n = k.shape[0]
+    fac, rhs = np.empty(n), np.empty(n)
+    lib().orc_ptrs_log_density(n, _ptr(k), _ptr(lam), PRECISIONS.get(precision, precision),
+                               _ptr(fac), _ptr(rhs))
+    return fac, rhs
 
 
 def exponential(pid, e, *, seed=160807058, stream=0, precision="fp64"):

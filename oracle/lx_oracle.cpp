@@ -266,6 +266,9 @@ struct PolicyF64 {
     *u1 = uniform_f64(w[0], w[1]);
     *u2 = uniform_f64(w[2], w[3]);
   }
+  // PTRS candidates per block of four words, and candidate s of a block
+  static constexpr uint32_t TRIALS_PER_BLOCK = 1;
+  static void candidate(const uint32_t w[4], uint32_t, R* u, R* v) { two_uniforms(w, u, v); }
   static double lambda_max() { return 1073741824.0; }  // 2^30
 };
 struct PolicyMixed {
@@ -277,16 +280,100 @@ struct PolicyMixed {
     *u1 = uniform_f32(w[0]);
     *u2 = uniform_f32(w[1]);
   }
+  // one 32-bit word per uniform: a block holds two PTRS candidates
+  static constexpr uint32_t TRIALS_PER_BLOCK = 2;
+  static void candidate(const uint32_t w[4], uint32_t s, R* u, R* v) {
+    count_ops(2 * OPS_UNIFORM);
+    *u = uniform_f32(w[2 * s]);
+    *v = uniform_f32(w[2 * s + 1]);
+  }
   static double lambda_max() { return 4194304.0; }  // 2^22: float k stays exact
 };
+
+// log(1 + d) for d > -1 from the policy's log: u = 1 + d rounded, then
+// log(u) scaled by d / (u - 1), which compensates the rounding of u
+// (Goldberg 1991, "What every computer scientist should know about
+// floating-point arithmetic", Theorem 4).
+template <class P>
+typename P::R log1p_r(typename P::R d) {
+  typedef typename P::R R;
+  R u = (R)1 + d;
+  count_ops(1);
+  if (u == (R)1) return d;
+  count_ops(2);
+  return P::ulog(u) * (d / (u - (R)1));
+}
+
+// phi(d) = log(1 + d) - d for d > -1.  For |d| <= 1/4 from the series
+// log(1 + d) = 2 atanh(s), s = d / (2 + d): phi = -d s + 2 s^3 (1/3 + s^2/5 +
+// ... + s^18/21), whose leading terms do not cancel (|s| <= 1/7, ten terms
+// reach double precision); beyond that log1p_r(d) - d.
+template <class P>
+typename P::R log1p_minus_id(typename P::R d) {
+  typedef typename P::R R;
+  if (std::fabs(d) <= (R)0.25) {
+    R s = d / ((R)2 + d);
+    R z = s * s;
+    R q = (R)(2.0 / 21.0);
+    q = std::fma(q, z, (R)(2.0 / 19.0));
+    q = std::fma(q, z, (R)(2.0 / 17.0));
+    q = std::fma(q, z, (R)(2.0 / 15.0));
+    q = std::fma(q, z, (R)(2.0 / 13.0));
+    q = std::fma(q, z, (R)(2.0 / 11.0));
+    q = std::fma(q, z, (R)(2.0 / 9.0));
+    q = std::fma(q, z, (R)(2.0 / 7.0));
+    q = std::fma(q, z, (R)(2.0 / 5.0));
+    q = std::fma(q, z, (R)(2.0 / 3.0));
+    count_ops(16);
+    return ((s * z) * q) - d * s;
+  }
+  count_ops(1);
+  return log1p_r<P>(d) - d;
+}
+
+// Log-density side of the PTRS acceptance test at candidate k >= 0 for mean
+// lam >= 10, in the policy's precision: returns (lhs_factor, rhs) such that
+// the candidate is accepted when log(q * lhs_factor) <= rhs, q being the
+// ratio v / (alpha * hat(u)).  This equals
+//   log q <= log p(k; lam) = k log lam - lam - log k!.
+// For k <= 17, log k! is the log of the exact product (lhs_factor = k!,
+// rhs = k log lam - lam).  For k > 17 log k! = log Gamma(n), n = k + 1, by
+// Stirling's series with four correction terms c(n).  With d = (lam - n)/n,
+// log(lam/n) = d + phi(d) and k = n - 1 this gives
+//   log p = k phi(d) - d - log(2 pi)/2 - c(n) - log(n)/2,
+// every term O(1) near the mode (no large terms cancel); the last term moves
+// left as the factor sqrt(n).
+template <class P>
+void ptrs_log_density(typename P::R kf, typename P::R lam, typename P::R* lhs_factor,
+                      typename P::R* rhs) {
+  typedef typename P::R R;
+  if (kf > (R)17) {
+    R n = kf + (R)1;
+    R rn = (R)1 / n;
+    R rn2 = rn * rn;
+    R corr = rn * ((R)(1.0 / 12.0) -
+                   rn2 * ((R)(1.0 / 360.0) - rn2 * ((R)(1.0 / 1260.0) - rn2 * (R)(1.0 / 1680.0))));
+    R d = (lam - n) / n;
+    *rhs = (kf * log1p_minus_id<P>(d) - d) - ((R)0x1.d67f1c864beb5p-1 + corr);
+    *lhs_factor = std::sqrt(n);
+    count_ops(18);
+  } else {
+    R f = (R)1;
+    for (R i = (R)2; i <= kf; i = i + (R)1) f = f * i;
+    *rhs = kf * P::ulog(lam) - lam;
+    *lhs_factor = f;
+    count_ops(4 + (uint64_t)kf);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Poisson sampler (Poisson leaping, Background section).
 //   lambda < lam_thr: sequential-search inversion of the CDF, one uniform.
 //   lambda >= lam_thr: PTRS, transformed rejection with squeeze
 //     (Hoermann 1993, "The transformed rejection method for generating
-//     Poisson random variables"), one (U, V) pair per round; the final
-//     log-density comparison is done in double in both precisions.
+//     Poisson random variables"), one (U, V) candidate per trial, all in the
+//     policy's precision; the final test is ptrs_log_density's.  Candidate t
+//     is candidate t mod TRIALS_PER_BLOCK of Philox block t / TRIALS_PER_BLOCK.
 // Returns -1 if lambda exceeds the policy's range (lane error).
 // ---------------------------------------------------------------------------
 template <class P>
@@ -317,14 +404,15 @@ int64_t poisson_sample(typename P::R lam, typename P::R lam_thr, int kcap, const
   R a = (R)-0.059 + (R)0.02483 * b;
   R inv_alpha = (R)1.1239 + (R)1.1328 / (b - (R)3.4);
   R vr = (R)0.9277 - (R)3.6224 / (b - (R)2);
-  double loglam = log_f64((double)lam);
-  double log_inv_alpha = log_f64((double)inv_alpha);
-  count_ops(12 + 2 * OPS_LOG);
+  count_ops(12);
   for (uint32_t trial = 0; trial < 64; ++trial) {
-    rng.block(e, site, trial, w);
-    count_ops(14);
+    if (trial % P::TRIALS_PER_BLOCK == 0) {
+      rng.block(e, site, trial / P::TRIALS_PER_BLOCK, w);
+      count_ops(2);
+    }
+    count_ops(12);
     R u0, v;
-    P::two_uniforms(w, &u0, &v);
+    P::candidate(w, trial % P::TRIALS_PER_BLOCK, &u0, &v);
     R u = u0 - (R)0.5;
     R us = (R)0.5 - std::fabs(u);
     R kf = std::floor((((R)2 * a) / us + b) * u + lam + (R)0.43);
@@ -332,9 +420,10 @@ int64_t poisson_sample(typename P::R lam, typename P::R lam_thr, int kcap, const
     if (us >= (R)0.07 && v <= vr) return (int64_t)kf;
     if (us < (R)0.013 && v > us) continue;
     R hat = a / (us * us) + b;
-    count_ops(12 + 2 * OPS_LOG);
-    double lhs = (log_f64((double)v) + log_inv_alpha) - log_f64((double)hat);
-    double rhs = (-(double)lam + (double)kf * loglam) - lfact_f64((double)kf);
+    R fac, rhs;
+    ptrs_log_density<P>(kf, lam, &fac, &rhs);
+    R lhs = P::ulog(((v * inv_alpha) * fac) / hat);
+    count_ops(4);
     if (lhs <= rhs) return (int64_t)kf;
   }
   return (int64_t)std::floor((double)lam);  // not reached in practice (p < 1e-60)
@@ -1104,6 +1193,25 @@ void orc_poisson(int64_t n, const double* lam, const uint32_t* pid, const uint32
       out[q] = poisson_sample<PolicyF64>(lam[q], lam_thr, kcap, rng, e[q], site[q]);
     else
       out[q] = poisson_sample<PolicyMixed>((float)lam[q], (float)lam_thr, kcap, rng, e[q], site[q]);
+  }
+}
+
+// The PTRS log-density split at (k, lam): factor f and right side r with
+// log p(k; lam) = r - log f (see ptrs_log_density), in the chosen precision.
+void orc_ptrs_log_density(int64_t n, const double* k, const double* lam, int32_t precision,
+                          double* fac, double* rhs) {
+  for (int64_t q = 0; q < n; ++q) {
+    if (precision == 0) {
+      double f, r;
+      ptrs_log_density<PolicyF64>(k[q], lam[q], &f, &r);
+      fac[q] = f;
+      rhs[q] = r;
+    } else {
+      float f, r;
+      ptrs_log_density<PolicyMixed>((float)k[q], (float)lam[q], &f, &r);
+      fac[q] = f;
+      rhs[q] = r;
+    }
   }
 }
 

@@ -200,9 +200,15 @@ struct F64 {
   __device__ static __forceinline__ R sqrt_(R v) { return __builtin_sqrt(v); }
   __device__ static __forceinline__ R floor_(R v) { return __builtin_floor(v); }
   __device__ static __forceinline__ R fabs_(R v) { return __builtin_fabs(v); }
+  __device__ static __forceinline__ R fma_(R a, R b, R c) { return __builtin_fma(a, b, c); }
   __device__ static __forceinline__ void uniforms(const Words4& w, R* u1, R* u2) {
     *u1 = uniform_f64(w.w0, w.w1);
     *u2 = uniform_f64(w.w2, w.w3);
+  }
+  // PTRS candidates per Philox block, and candidate s of a block
+  static constexpr u32 TRIALS_PER_BLOCK = 1;
+  __device__ static __forceinline__ void candidate(const Words4& w, u32, R* u, R* v) {
+    uniforms(w, u, v);
   }
   __device__ static __forceinline__ double lambda_max() { return 1073741824.0; }
   __device__ static __forceinline__ R inf() { return LX_INF_F64; }
@@ -216,9 +222,16 @@ struct Mixed {
   __device__ static __forceinline__ R sqrt_(R v) { return __builtin_sqrtf(v); }
   __device__ static __forceinline__ R floor_(R v) { return __builtin_floorf(v); }
   __device__ static __forceinline__ R fabs_(R v) { return __builtin_fabsf(v); }
+  __device__ static __forceinline__ R fma_(R a, R b, R c) { return __builtin_fmaf(a, b, c); }
   __device__ static __forceinline__ void uniforms(const Words4& w, R* u1, R* u2) {
     *u1 = uniform_f32(w.w0);
     *u2 = uniform_f32(w.w1);
+  }
+  // one 32-bit word per uniform: a block holds two PTRS candidates
+  static constexpr u32 TRIALS_PER_BLOCK = 2;
+  __device__ static __forceinline__ void candidate(const Words4& w, u32 s, R* u, R* v) {
+    *u = uniform_f32(s ? w.w2 : w.w0);
+    *v = uniform_f32(s ? w.w3 : w.w1);
   }
   __device__ static __forceinline__ double lambda_max() { return 4194304.0; }
   __device__ static __forceinline__ R inf() { return LX_INF_F32; }
@@ -226,24 +239,88 @@ struct Mixed {
 
 // ---------------------------------------------------------------------------
 // Poisson sampler: inversion below lam_thr (one uniform), PTRS of Hoermann
-// (1993) above (one (U, V) pair per round, final log-density test in double).
-// Returns -1 when lam is beyond the policy's range.
+// (1993) above, all in the policy's precision.  PTRS candidate t is candidate
+// t mod TRIALS_PER_BLOCK of Philox block t / TRIALS_PER_BLOCK.  Returns -1
+// when lam is beyond the policy's range.
 // ---------------------------------------------------------------------------
+
+// log(1 + d), d > -1: log of the rounded u = 1 + d scaled by d / (u - 1)
+// (Goldberg 1991, Theorem 4).
 template <class P>
-__device__ __noinline__ long long poisson_ptrs(typename P::R lam, const Key& key, u32 pid, u32 e,
-                                               u32 site) {
+__device__ __forceinline__ typename P::R log1p_r(typename P::R d) {
+  typedef typename P::R R;
+  const R u = (R)1 + d;
+  if (u == (R)1) return d;
+  return P::ulog(u) * (d / (u - (R)1));
+}
+
+// phi(d) = log(1 + d) - d.  For |d| <= 1/4 by the atanh series in
+// s = d / (2 + d): phi = 2 s^3 (1/3 + s^2/5 + ... + s^18/21) - d s; else
+// log1p_r(d) - d.
+template <class P>
+__device__ __forceinline__ typename P::R log1p_minus_id(typename P::R d) {
+  typedef typename P::R R;
+  if (P::fabs_(d) <= (R)0.25) {
+    const R s = d / ((R)2 + d);
+    const R z = s * s;
+    R q = (R)(2.0 / 21.0);
+    q = P::fma_(q, z, (R)(2.0 / 19.0));
+    q = P::fma_(q, z, (R)(2.0 / 17.0));
+    q = P::fma_(q, z, (R)(2.0 / 15.0));
+    q = P::fma_(q, z, (R)(2.0 / 13.0));
+    q = P::fma_(q, z, (R)(2.0 / 11.0));
+    q = P::fma_(q, z, (R)(2.0 / 9.0));
+    q = P::fma_(q, z, (R)(2.0 / 7.0));
+    q = P::fma_(q, z, (R)(2.0 / 5.0));
+    q = P::fma_(q, z, (R)(2.0 / 3.0));
+    return ((s * z) * q) - d * s;
+  }
+  return log1p_r<P>(d) - d;
+}
+
+// The PTRS acceptance test at candidate k (mean lam >= 10) is
+// log(ratio * factor) <= rhs with log p(k; lam) = rhs - log(factor): for
+// k <= 17 factor = k! (exact product) and rhs = k log lam - lam; beyond,
+// Stirling's series for log Gamma(k + 1) with four correction terms c(n),
+// n = k + 1, d = (lam - n) / n, rhs = k phi(d) - d - log(2 pi)/2 - c(n) and
+// factor = sqrt(n).  Every term is O(1) near the mode.
+template <class P>
+__device__ __forceinline__ void ptrs_log_density(typename P::R kf, typename P::R lam,
+                                                 typename P::R* factor, typename P::R* rhs) {
+  typedef typename P::R R;
+  if (kf > (R)17) {
+    const R n = kf + (R)1;
+    const R rn = (R)1 / n;
+    const R rn2 = rn * rn;
+    const R corr =
+        rn * ((R)(1.0 / 12.0) -
+              rn2 * ((R)(1.0 / 360.0) - rn2 * ((R)(1.0 / 1260.0) - rn2 * (R)(1.0 / 1680.0))));
+    const R d = (lam - n) / n;
+    *rhs = (kf * log1p_minus_id<P>(d) - d) - ((R)0x1.d67f1c864beb5p-1 + corr);
+    *factor = P::sqrt_(n);
+  } else {
+    R f = (R)1;
+    for (R i = (R)2; i <= kf; i = i + (R)1) f = f * i;
+    *rhs = kf * P::ulog(lam) - lam;
+    *factor = f;
+  }
+}
+
+template <class P>
+__device__ __forceinline__ long long poisson_ptrs(typename P::R lam, const Key& key, u32 pid, u32 e,
+                                                  u32 site) {
   typedef typename P::R R;
   const R slam = P::sqrt_(lam);
   const R b = (R)0.931 + (R)2.53 * slam;
   const R a = (R)-0.059 + (R)0.02483 * b;
   const R inv_alpha = (R)1.1239 + (R)1.1328 / (b - (R)3.4);
   const R vr = (R)0.9277 - (R)3.6224 / (b - (R)2);
-  const double loglam = log_f64((double)lam);
-  const double log_inv_alpha = log_f64((double)inv_alpha);
+  Words4 w = Words4{0u, 0u, 0u, 0u};
   for (u32 trial = 0; trial < 64; ++trial) {
-    const Words4 w = draw_block(key, pid, e, site, trial);
+    if (trial % P::TRIALS_PER_BLOCK == 0u)
+      w = draw_block(key, pid, e, site, trial / P::TRIALS_PER_BLOCK);
     R u0, v;
-    P::uniforms(w, &u0, &v);
+    P::candidate(w, trial % P::TRIALS_PER_BLOCK, &u0, &v);
     const R u = u0 - (R)0.5;
     const R us = (R)0.5 - P::fabs_(u);
     const R kf = P::floor_((((R)2 * a) / us + b) * u + lam + (R)0.43);
@@ -251,8 +328,9 @@ __device__ __noinline__ long long poisson_ptrs(typename P::R lam, const Key& key
     if (us >= (R)0.07 && v <= vr) return (long long)kf;
     if (us < (R)0.013 && v > us) continue;
     const R hat = a / (us * us) + b;
-    const double lhs = (log_f64((double)v) + log_inv_alpha) - log_f64((double)hat);
-    const double rhs = (-(double)lam + (double)kf * loglam) - lfact_f64((double)kf);
+    R fac, rhs;
+    ptrs_log_density<P>(kf, lam, &fac, &rhs);
+    const R lhs = P::ulog(((v * inv_alpha) * fac) / hat);
     if (lhs <= rhs) return (long long)kf;
   }
   return (long long)__builtin_floor((double)lam);
@@ -280,6 +358,15 @@ __device__ __forceinline__ long long poisson_sample(typename P::R lam, typename 
     return k;
   }
   return poisson_ptrs<P>(lam, key, pid, e, site);
+}
+
+// Out-of-line form for kernels that sample many reactions per lane (keeps one
+// copy of the rejection loop instead of one per unrolled call).
+template <class P>
+__device__ __noinline__ long long poisson_sample_call(typename P::R lam, typename P::R lam_thr,
+                                                      int kcap, const Key& key, u32 pid, u32 e,
+                                                      u32 site) {
+  return poisson_sample<P>(lam, lam_thr, kcap, key, pid, e, site);
 }
 
 // ---------------------------------------------------------------------------

@@ -621,8 +621,11 @@ struct Lane {
       for (int j = 0; j < M; ++j) {
         k[j] = 0;
         if ((ncr >> j) & 1u) {
-          const long long kj =
-              poisson_sample<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
+          long long kj;
+          if constexpr (M > 4)
+            kj = poisson_sample_call<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
+          else
+            kj = poisson_sample<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
           overflow = overflow || kj < 0;
           k[j] = kj;
         }
@@ -642,9 +645,14 @@ struct Lane {
           }
         }
         long long kj = 0;
-        if (nc)
-          kj = poisson_sample<P>(aj * tau_rr, lam_thr, prm.kcap, key, pid, ea,
-                                 (u32)(g * TPL + sub));
+        if (nc) {
+          if constexpr ((M + TPL - 1) / TPL > 4)
+            kj = poisson_sample_call<P>(aj * tau_rr, lam_thr, prm.kcap, key, pid, ea,
+                                        (u32)(g * TPL + sub));
+          else
+            kj = poisson_sample<P>(aj * tau_rr, lam_thr, prm.kcap, key, pid, ea,
+                                   (u32)(g * TPL + sub));
+        }
 #pragma unroll
         for (int q = 0; q < TPL; ++q) {
           if (g * TPL + q < M) {

@@ -240,6 +240,38 @@ def test_poisson_law(orc, lam, precision):
     assert abs(z_mean) < 4.5
 
 
+def _logpmf_mp(k, lam):
+    import mpmath
+    with mpmath.workdps(40):
+        return float(k * mpmath.log(lam) - lam - mpmath.loggamma(k + 1))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("mixed", 2e-6)])
+def test_ptrs_log_density_is_the_poisson_log_pmf(orc, precision, tol):
+    # The acceptance test's right side minus the log of its left factor is
+    # log p(k; lam) (Hoermann 1993's final test), checked against 40-digit
+    # arithmetic: the exact-product branch (k <= 17), the Stirling branch with
+    # its series for log(1 + d) - d (|d| <= 1/4) and with the log beyond, at
+    # the means the sampler sees (10 to 2^22).  The bound is a few units in the
+    # last place of the policy's precision, relative to 1 + |log p|.
+    ks, lams = [], []
+    for lam in (10.0, 10.5, 17.3, 30.0, 250.0, 1e4, 1e6, 4e6):
+        r = math.sqrt(lam)
+        kk = np.concatenate([np.arange(0, 60), np.round(lam + r * np.linspace(-8, 8, 41)),
+                             np.round(lam * np.array([0.5, 0.79, 0.81, 1.2, 1.26, 2.0]))])
+        kk = np.unique(kk[kk >= 0])
+        ks.append(kk)
+        lams.append(np.full(kk.shape, lam))
+    k, lam = np.concatenate(ks), np.concatenate(lams)
+    if precision == "mixed":
+        lam = lam.astype(np.float32).astype(np.float64)
+    fac, rhs = orc.ptrs_log_density(k, lam, precision=precision)
+    got = rhs - np.log(fac)
+    ref = np.array([_logpmf_mp(int(a), float(b)) for a, b in zip(k, lam)])
+    err = np.abs(got - ref) / (1.0 + np.abs(ref))
+    assert err.max() < tol, (k[err.argmax()], lam[err.argmax()], err.max())
+
+
 def test_poisson_large_lambda_fp64(orc):
     lam = 1e8
     n = 50000
