@@ -143,9 +143,14 @@ const char* lx_last_error(void);
  *                     consumed by reaction j; order_j = sum_i m_ij <= 3.
  *   product_coeff     host int32 [M][N], p_ij >= 0 molecules produced.
  * g_j(X) = prod_i C(X_i, m_ij) (distinct-combination convention).
- * Errors: LX_E_INVALID for a bad table or N*M too large (M <= 32 and
- * N <= 16 for the register-resident kernels).  *out receives a handle owned
- * by the caller and released with lx_network_destroy. */
+ * Sizes: N <= 64, M <= 256.  Networks with N <= 16 and M <= 32 run kernels
+ * whose per-lane state lives in registers; larger ones run kernels that keep
+ * per-lane arrays in the lane-interleaved private segment and read the
+ * stoichiometry as compressed tables (one lane per trajectory; no network
+ * sets, no particle filter, lanes_per_traj and regroup must be 0).
+ * Errors: LX_E_INVALID for a bad table or a network above those sizes.
+ * *out receives a handle owned by the caller and released with
+ * lx_network_destroy. */
 lx_status lx_network_create(int32_t N, int32_t M, const int32_t* reactant_order,
                             const int32_t* product_coeff, lx_network* out);
 
@@ -298,7 +303,8 @@ lx_status lx_test_gamma(int64_t n, const double* shape, const uint32_t* pid, con
 lx_status lx_test_exponential(int64_t n, const uint32_t* pid, const uint32_t* e, uint64_t seed,
                               uint32_t stream_id, int32_t precision, double* out, void* stream);
 /* Step decision for Q states of a network: propensities a [Q][M] (as double),
- * critical and equilibrium masks crit/eq [Q] (bit j = reaction j), tau [Q][2]
+ * critical and equilibrium masks crit/eq [Q][W], W = ceil(M/32) words per
+ * state (reaction j is bit j % 32 of word j / 32; W = 1 up to 32 reactions), tau [Q][2]
  * = (tau_ex, tau_im or +inf), action [Q] (0 explicit leap, 1 implicit leap,
  * 2 SSA burst, 3 absorbing).  theta [Q][M], x [Q][N].  Uses opt->precision
  * and the control constants; eps and mode as in lx_simulate. */

@@ -28,7 +28,7 @@
 #include <vector>
 
 #include "lx.h"
-#include "lx_embedded.inc"  // lx_src_params, lx_src_device, lx_src_sim (generated)
+#include "lx_embedded.inc"  // lx_src_params, lx_src_device, lx_src_sim, lx_src_sim_large (generated)
 #include "lx_params.h"
 
 static_assert(sizeof(lx_stats) == sizeof(lx::Stats), "lx_stats layout");
@@ -69,8 +69,10 @@ lx_status hip_fail(hipError_t e, const char* what) {
   return fail(LX_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-const int MAX_M = 32;
-const int MAX_N = 16;
+const int MAX_M = 256;  // networks up to 64 x 256 (large-network kernels beyond 16 x 32)
+const int MAX_N = 64;
+const int REG_M = 32;  // register-resident kernels
+const int REG_N = 16;
 // The register-resident lane state needs well over 128 VGPRs; blocks of more
 // than four waves per SIMD would force spills (and were refused at dispatch),
 // so blocks are limited to 256 threads.
@@ -173,6 +175,7 @@ struct Kernel {
 // ---------------------------------------------------------------------------
 struct lx_network_s {
   int N = 0, M = 0, npairs = 0;
+  bool large = false;  // beyond the register-resident limits: lx_sim_large.h kernels
   std::vector<int> ro, nu, phi, partner;
   std::string netsrc;
   std::mutex mu;
@@ -206,11 +209,46 @@ std::string vec_src(const char* name, const std::vector<int>& v) {
   return s.str();
 }
 
+// Compressed rows of an M x N (or transposed) table: for each row the
+// columns with a nonzero entry, ascending, and their values.
+void csr_src(std::ostringstream& s, const char* ptr, const char* idx, const char* val,
+             const std::vector<int>& t, int rows, int cols, bool transpose, bool reactants) {
+  std::vector<int> p(1, 0), ix, vv;
+  for (int r = 0; r < rows; ++r) {
+    for (int c = 0; c < cols; ++c) {
+      const size_t at = transpose ? (size_t)c * rows + r : (size_t)r * cols + c;
+      const int v = t[at];
+      if (v == 0 || (reactants && v < 0)) continue;
+      ix.push_back(c);
+      vv.push_back(v);
+    }
+    p.push_back((int)ix.size());
+  }
+  if (ix.empty()) {  // keep arrays non-empty
+    ix.push_back(0);
+    vv.push_back(0);
+  }
+  s << vec_src(ptr, p) << vec_src(idx, ix) << vec_src(val, vv);
+}
+
 // Compile-time description of the network for the kernel source: a traits
-// struct named LxNet<k> (the "@" placeholder is replaced by k).
+// struct named LxNet<k> (the "@" placeholder is replaced by k).  Small
+// networks carry dense tables (unrolled kernels); large ones compressed rows.
 std::string network_source(const lx_network_s& n) {
   std::ostringstream s;
   s << "struct LxNet@ {\n";
+  if (n.large) {
+    s << "  static constexpr int LARGE = 1;\n";
+    s << "  static constexpr int N = " << n.N << ";\n  static constexpr int M = " << n.M << ";\n";
+    s << "  static constexpr int NPAIRS = " << n.npairs << ";\n";
+    csr_src(s, "RX_PTR", "RX_SP", "RX_RO", n.ro, n.M, n.N, false, true);
+    csr_src(s, "NJ_PTR", "NJ_SP", "NJ_V", n.nu, n.M, n.N, false, false);
+    csr_src(s, "NI_PTR", "NI_RX", "NI_V", n.nu, n.N, n.M, true, false);
+    s << vec_src("PHI", n.phi);
+    s << vec_src("PARTNER", n.partner);
+    s << "};\n";
+    return s.str();
+  }
   s << "  static constexpr int N = " << n.N << ";\n  static constexpr int M = " << n.M << ";\n";
   s << "  static constexpr int NPAIRS = " << n.npairs << ";\n";
   s << table_src("RO", n.ro, n.M, n.N);
@@ -237,8 +275,10 @@ std::string kernel_source(const lx_network_s& net, const char* variant, int prec
   src << "#define LX_BLOCK " << block << "\n";
   if (strcmp(variant, "hooks") == 0) src << "#define LX_HOOKS 1\n";
   if (strcmp(variant, "batched") == 0) src << "#define LX_BATCHED 1\n";
+  if (net.large) src << "#define LX_LARGE 1\n";
   src << lx_src_params << "\n" << lx_src_device << "\n" << named_net(net, 0)
       << "typedef LxNet0 LxNet;\n" << lx_src_sim;
+  if (net.large) src << "\n" << lx_src_sim_large;
   return src.str();
 }
 
@@ -429,6 +469,38 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
   lx_status st = fill_params(o, P, t_end, eps, mode, &L->prm);
   if (st != LX_OK) return st;
   if (P == 0) return LX_OK;
+  if (net->large) {
+    // One lane per trajectory; the plain schedule gives every lane one
+    // trajectory, the batched one refills lanes from the block's range.
+    if (o.lanes_per_traj > 1 || o.regroup > 0)
+      return fail(LX_E_UNSUPPORTED,
+                  "networks beyond 16 species or 32 reactions run one lane per trajectory "
+                  "without regrouping (lanes_per_traj and regroup must be 0)");
+    const bool batched = o.schedule == LX_SCHED_BATCHED;
+    L->batched = true;
+    L->block = o.block_size ? o.block_size : (batched ? 256 : 64);
+    st = get_kernel(net, "large", o.precision, L->block, "lx_sim_large", &L->fn, 1);
+    if (st != LX_OK) return st;
+    long long per_block = L->block;
+    int lanes = 64;
+    if (batched) {
+      int cus = 0;
+      st = device_cus(&cus);
+      if (st != LX_OK) return st;
+      lanes = traj_per_wave(o, P, cus);
+      const long long round = (long long)(L->block / 64) * lanes;
+      const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
+      per_block = (P + max_grid - 1) / max_grid;
+      if (per_block < round) per_block = round;
+    }
+    L->prm.per_block = per_block;
+    L->prm.lanes = lanes;
+    L->prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
+    L->prm.regroup = 0;
+    L->grid = (P + per_block - 1) / per_block;
+    if (L->grid > 0x7fffffffLL) return fail(LX_E_INVALID, "P too large for one launch");
+    return LX_OK;
+  }
   L->batched = o.schedule == LX_SCHED_BATCHED;
   L->block = o.block_size ? o.block_size : (L->batched ? 256 : 64);
   st = get_kernel(net, L->batched ? "batched" : "plain", o.precision, L->block,
@@ -501,11 +573,12 @@ lx_status lx_network_create(int32_t N, int32_t M, const int32_t* ro, const int32
   if (N < 1 || M < 1) return fail(LX_E_INVALID, "need N >= 1 and M >= 1");
   if (!ro || !pc) return fail(LX_E_INVALID, "null stoichiometry table");
   if (M > MAX_M || N > MAX_N)
-    return fail(LX_E_INVALID, "network too large for the register-resident kernels (M <= 32, N <= 16)");
+    return fail(LX_E_INVALID, "network too large (need N <= 64 species, M <= 256 reactions)");
   lx_network_s* n = new (std::nothrow) lx_network_s();
   if (!n) return fail(LX_E_NOMEM, "out of host memory");
   n->N = N;
   n->M = M;
+  n->large = M > REG_M || N > REG_N;
   n->ro.assign((size_t)M * N, 0);
   n->nu.assign((size_t)M * N, 0);
   std::vector<int> order(M, 0);
@@ -581,9 +654,8 @@ lx_status lx_network_prepare(lx_network net, int32_t precision, int32_t schedule
     return fail(LX_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
   const int block = block_size ? block_size : (schedule == LX_SCHED_BATCHED ? 256 : 64);
   std::vector<char> code;
-  return compile_source(
-      kernel_source(*net, schedule == LX_SCHED_BATCHED ? "batched" : "plain", precision, block, 1),
-      &code);
+  const char* variant = net->large ? "large" : (schedule == LX_SCHED_BATCHED ? "batched" : "plain");
+  return compile_source(kernel_source(*net, variant, precision, block, 1), &code);
 }
 
 lx_status lx_network_destroy(lx_network net) {
@@ -631,6 +703,8 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
   for (int k = 0; k < K; ++k) {
     const lx_set_item& it = items[k];
     if (!it.net || it.P < 0) return fail(LX_E_INVALID, "bad set item");
+    if (it.net->large)
+      return fail(LX_E_UNSUPPORTED, "network sets take networks of at most 16 species and 32 reactions");
     if (it.P > 0 && (!it.theta || !it.x0 || !it.x_out || !it.r_out || !it.G_out))
       return fail(LX_E_INVALID, "null input/output pointer in set item");
     lx_options ok = o;
@@ -821,6 +895,8 @@ lx_status pf_check(const lx_pf_problem* pb, double eps, int32_t mode, const lx_o
                    lx_options* o, SimLaunch* L, lx::PfWork* w) {
   if (!pb || !pb->net) return fail(LX_E_INVALID, "null problem or network");
   const lx_pf_problem& q = *pb;
+  if (q.net->large)
+    return fail(LX_E_UNSUPPORTED, "the particle filter takes networks of at most 16 species and 32 reactions");
   if (q.P < 1 || q.P > (1LL << 23) || q.K < 1) return fail(LX_E_INVALID, "need 1 <= P <= 2^23, K >= 1");
   if (q.obs_species < 0 || q.obs_species >= q.net->N) return fail(LX_E_INVALID, "bad obs_species");
   if (!(q.dt > 0.0) || !std::isfinite(q.dt) || !(q.obs_sd > 0.0) || !std::isfinite(q.obs_sd))

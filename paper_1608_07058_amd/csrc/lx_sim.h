@@ -3,7 +3,8 @@
 // Compiled at run time by hipRTC after lx_device.h, lx_params.h and a
 // generated block that defines one traits struct per network (LxNet0, LxNet1,
 // ...; LxNet is the first) with static constexpr members:
-//   N, M         species and reactions (M <= 32 here)
+//   N, M         species and reactions (M <= 32, N <= 16 here; larger
+//                networks run the kernels of lx_sim_large.h)
 //   RO[M][N]     reactant orders m_ij
 //   NU[M][N]     net changes nu_ij = p_ij - m_ij
 //   PHI[N]       case of the tau-bound factor of each species (0: not a reactant)
@@ -822,7 +823,7 @@ struct Lane {
 
 }  // namespace lx
 
-#if !defined(LX_BATCHED) && !defined(LX_SET)
+#if !defined(LX_BATCHED) && !defined(LX_SET) && !defined(LX_LARGE)
 // Plain form: lane = particle for life, 64 lanes per wave.
 extern "C" __global__ void __launch_bounds__(LX_BLOCK)
     lx_sim_plain(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
@@ -977,7 +978,7 @@ __device__ __forceinline__ void run_sched(long long blk, const double* __restric
 }  // namespace lx
 #endif
 
-#ifdef LX_BATCHED
+#if defined(LX_BATCHED) && !defined(LX_LARGE)
 extern "C" __global__ void __launch_bounds__(LX_BLOCK)
     lx_sim_batched(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
                    int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
@@ -986,7 +987,7 @@ extern "C" __global__ void __launch_bounds__(LX_BLOCK)
 }
 #endif
 
-#ifdef LX_HOOKS
+#if defined(LX_HOOKS) && !defined(LX_LARGE)
 // Step decision on fixed states (test hook).
 extern "C" __global__ void __launch_bounds__(64)
     lx_hook_tau(const double* __restrict__ theta, const int* __restrict__ xs, double* a_out,

@@ -1,0 +1,638 @@
+// lx_sim_large.h -- one trajectory per lane for networks beyond the
+// register-resident kernels of lx_sim.h (up to 64 species, 256 reactions).
+//
+// The method and every arithmetic operation, in the same order, are those of
+// lx::Lane; only the storage differs.  The generated traits struct of a large
+// network (LxNet, LARGE = 1) holds compressed stoichiometry instead of dense
+// tables:
+//   RX_PTR[M+1], RX_SP[], RX_RO[]  reactants of reaction j (ascending species)
+//   NJ_PTR[M+1], NJ_SP[], NJ_V[]   nonzero net changes of reaction j (ascending species)
+//   NI_PTR[N+1], NI_RX[], NI_V[]   nonzero net changes of species i (ascending reactions)
+//   PHI[N], PARTNER[M], NPAIRS
+// Loops over species and reactions run at run time with wave-uniform trip
+// counts and table indices (scalar loads).  The per-lane arrays (theta, r, G,
+// g, a, reaction sets, counts, the Newton system) are private arrays indexed
+// at run time, which live in the private segment; it is interleaved by lane,
+// so a uniform index across a wave is one contiguous access.
+#pragma once
+
+namespace lx {
+
+template <class NET>
+__device__ __forceinline__ double g_large(int j, const int* x) {
+  double gj = 1.0;
+  for (int q = NET::RX_PTR[j]; q < NET::RX_PTR[j + 1]; ++q)
+    gj = gj * binom_real((double)x[NET::RX_SP[q]], NET::RX_RO[q]);
+  return gj;
+}
+
+template <class NET>
+__device__ __forceinline__ double g_large_y(int j, const double* y) {
+  double gj = 1.0;
+  for (int q = NET::RX_PTR[j]; q < NET::RX_PTR[j + 1]; ++q)
+    gj = gj * binom_real(y[NET::RX_SP[q]], NET::RX_RO[q]);
+  return gj;
+}
+
+// d g_j / d y_k.
+template <class NET>
+__device__ __forceinline__ double dg_large(int j, int k, const double* y) {
+  double gj = 1.0;
+  for (int q = NET::RX_PTR[j]; q < NET::RX_PTR[j + 1]; ++q) {
+    const int i = NET::RX_SP[q];
+    gj = gj * (i == k ? binom_real_deriv(y[i], NET::RX_RO[q]) : binom_real(y[i], NET::RX_RO[q]));
+  }
+  return gj;
+}
+
+template <class P, class NET>
+struct LaneL {
+  typedef typename P::R R;
+  static constexpr int N = NET::N;
+  static constexpr int M = NET::M;
+
+  u32 pid;
+  double th[M];
+  R thr[M];
+  int x[N];
+  int r[M];
+  double G[M];
+  double t;
+  u32 e;
+  int status;
+  double g[M];
+  R a[M];
+  R a0, a0c;
+  unsigned char crit[M], ncr[M], eq[M];
+  bool plan, gvalid, implicit, any_eq;
+  R tau_p;
+  int ssa_left;
+  u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip;
+  long long n_nit;
+
+  __device__ __forceinline__ bool active(const SimParams& prm) const {
+    return status == LANE_OK && t < prm.t_end;
+  }
+
+  __device__ __forceinline__ void load(long long p, const double* __restrict__ theta,
+                                       const int* __restrict__ x0, const int* r_in,
+                                       const double* G_in, const SimParams& prm) {
+    pid = prm.pid_base + (u32)p * prm.pid_stride;
+    bool bad = false;
+    for (int j = 0; j < M; ++j) {
+      th[j] = theta[p * M + j];
+      thr[j] = (R)th[j];
+      bad = bad || !(th[j] >= 0.0) || th[j] == LX_INF_F64;
+      r[j] = prm.accumulate ? r_in[p * M + j] : 0;
+      G[j] = prm.accumulate ? G_in[p * M + j] : 0.0;
+    }
+    for (int i = 0; i < N; ++i) {
+      x[i] = x0[p * N + i];
+      bad = bad || x[i] < 0;
+    }
+    status = bad ? LANE_BAD_INPUT : LANE_OK;
+    t = prm.t_start;
+    e = 0;
+    plan = false;
+    gvalid = false;
+    implicit = false;
+    ssa_left = 0;
+    n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = 0;
+  }
+
+  __device__ __forceinline__ void store(long long p, int* x_out, int* r_out, double* G_out,
+                                        Stats* stats) const {
+    for (int i = 0; i < N; ++i) x_out[p * N + i] = x[i];
+    for (int j = 0; j < M; ++j) {
+      r_out[p * M + j] = r[j];
+      G_out[p * M + j] = G[j];
+    }
+    if (stats) {
+      Stats s;
+      s.status = status;
+      s.pad = 0;
+      s.t_final = t;
+      s.steps_ssa = n_ssa;
+      s.steps_explicit = n_ex;
+      s.steps_implicit = n_im;
+      s.rejections = n_rej;
+      s.newton_iters = n_nit;
+      s.newton_fail = n_nfail;
+      s.kclip = n_clip;
+      s.attempts = e;
+      stats[p] = s;
+    }
+  }
+
+  // a_j = theta_j g_j (Background section); a0 summed in ascending j.
+  __device__ __forceinline__ void propensities() {
+    const bool fresh = !gvalid;
+    a0 = (R)0;
+    for (int j = 0; j < M; ++j) {
+      if (fresh) g[j] = g_large<NET>(j, x);
+      a[j] = thr[j] * (R)g[j];
+      a0 = a0 + a[j];
+    }
+    gvalid = true;
+  }
+
+  __device__ __forceinline__ R phi(int i) const {
+    const int c = NET::PHI[i];
+    if (c == 1) return (R)1;
+    if (c == 2) return (R)2;
+    if (c == 4) return (R)3;
+    const R xm1 = (R)(x[i] - 1 > 1 ? x[i] - 1 : 1);
+    if (c == 3) return (R)2 + (R)1 / xm1;
+    if (c == 5) return (R)1.5 * ((R)2 + (R)1 / xm1);
+    const R xm2 = (R)(x[i] - 2 > 1 ? x[i] - 2 : 1);
+    return ((R)3 + (R)1 / xm1) + (R)2 / xm2;
+  }
+
+  // Tau selection (Cao 2006) over the non-critical reactions, without those
+  // in partial equilibrium when `skip_eq`.
+  __device__ __forceinline__ R tau_select(bool skip_eq, R eps) const {
+    R tau = P::inf();
+    for (int i = 0; i < N; ++i) {
+      if (NET::PHI[i] == 0) continue;
+      R mu = (R)0, s2 = (R)0;
+      for (int q = NET::NI_PTR[i]; q < NET::NI_PTR[i + 1]; ++q) {
+        const int j = NET::NI_RX[q];
+        const int v = NET::NI_V[q];
+        if (ncr[j] && !(skip_eq && eq[j])) {
+          mu = mu + (R)v * a[j];
+          s2 = s2 + (R)(v * v) * a[j];
+        }
+      }
+      R num = eps * (R)x[i];
+      if (NET::PHI[i] != 1) num = num / phi(i);
+      const R bound = num < (R)1 ? (R)1 : num;
+      const R t1 = (mu != (R)0) ? bound / P::fabs_(mu) : P::inf();
+      const R t2 = (s2 != (R)0) ? (bound * bound) / s2 : P::inf();
+      const R ti = t2 < t1 ? t2 : t1;
+      tau = ti < tau ? ti : tau;
+    }
+    return tau;
+  }
+
+  __device__ __forceinline__ void decide(const SimParams& prm, R* tau_ex_out, R* tau_im_out) {
+    a0c = (R)0;
+    for (int j = 0; j < M; ++j) {
+      int L = 0x7fffffff;
+      for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q) {
+        const int v = NET::NJ_V[q];
+        if (v < 0) {
+          const int qq = x[NET::NJ_SP[q]] / (-v);
+          L = qq < L ? qq : L;
+        }
+      }
+      const bool pos = a[j] > (R)0;
+      const bool c = pos && L < prm.n_c;
+      crit[j] = c ? 1 : 0;
+      ncr[j] = (pos && !c) ? 1 : 0;
+      eq[j] = 0;
+      if (c) a0c = a0c + a[j];
+    }
+    const R eps = (R)prm.eps;
+    const R tau_ex = tau_select(false, eps);
+    implicit = false;
+    tau_p = tau_ex;
+    *tau_ex_out = tau_ex;
+    *tau_im_out = P::inf();
+    any_eq = false;
+    if (NET::NPAIRS > 0 && prm.mode == MODE_ADAPTIVE) {
+      const R delta = (R)prm.delta;
+      for (int j = 0; j < M; ++j) {
+        const int k = NET::PARTNER[j];
+        if (k <= j) continue;
+        if (ncr[j] && ncr[k]) {
+          const R lo = a[k] < a[j] ? a[k] : a[j];
+          if (P::fabs_(a[j] - a[k]) <= delta * lo) {
+            eq[j] = 1;
+            eq[k] = 1;
+            any_eq = true;
+          }
+        }
+      }
+      if (any_eq) {
+        const R tau_im = tau_select(true, eps);
+        *tau_im_out = tau_im;
+        if (tau_im > (R)prm.n_stiff * tau_ex) {
+          implicit = true;
+          tau_p = tau_im;
+        }
+      }
+    }
+    plan = true;
+  }
+
+  __device__ __forceinline__ void make_plan(const SimParams& prm) {
+    R tau_ex, tau_im;
+    decide(prm, &tau_ex, &tau_im);
+  }
+
+  __device__ __forceinline__ void absorb(const SimParams& prm) {
+    const double rem = prm.t_end - t;
+    for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * rem;
+    t = prm.t_end;
+  }
+
+  // One SSA step (Gillespie 1977 direct method) with exact G.
+  __device__ __forceinline__ void ssa_step(const SimParams& prm, const Key& key) {
+    const Words4 w = draw_block(key, pid, e, SITE_SSA, 0);
+    R u1, u2;
+    P::uniforms(w, &u1, &u2);
+    e = e + 1;
+    n_ssa += 1;
+    const R E = -P::ulog(u1);
+    const double tau_s = (double)(E / a0);
+    const double rem = prm.t_end - t;
+    if (tau_s >= rem) {
+      absorb(prm);
+      return;
+    }
+    const R thr_ = u2 * a0;
+    R cum = (R)0;
+    int jf = -1, jlast = -1;
+    for (int j = 0; j < M; ++j) {
+      if (a[j] > (R)0) jlast = j;
+      cum = cum + a[j];
+      if (cum > thr_) {
+        jf = j;
+        break;
+      }
+    }
+    if (jf < 0) jf = jlast;
+    for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * tau_s;
+    for (int q = NET::NJ_PTR[jf]; q < NET::NJ_PTR[jf + 1]; ++q) x[NET::NJ_SP[q]] += NET::NJ_V[q];
+    r[jf] = r[jf] + 1;
+    t = t + tau_s;
+    gvalid = false;
+  }
+
+  // Dense LU with partial pivoting (first maximal pivot); A row-major N x N.
+  __device__ static bool lu_solve(double* A, double* b) {
+    for (int c = 0; c < N; ++c) {
+      int piv = c;
+      double best = __builtin_fabs(A[c * N + c]);
+      for (int rr = c + 1; rr < N; ++rr) {
+        const double v = __builtin_fabs(A[rr * N + c]);
+        if (v > best) {
+          best = v;
+          piv = rr;
+        }
+      }
+      if (!(best > 0.0)) return false;
+      if (piv != c) {
+        for (int q = 0; q < N; ++q) {
+          const double tmp = A[c * N + q];
+          A[c * N + q] = A[piv * N + q];
+          A[piv * N + q] = tmp;
+        }
+        const double tb = b[c];
+        b[c] = b[piv];
+        b[piv] = tb;
+      }
+      for (int rr = c + 1; rr < N; ++rr) {
+        const double l = A[rr * N + c] / A[c * N + c];
+        for (int q = c; q < N; ++q) A[rr * N + q] = A[rr * N + q] - l * A[c * N + q];
+        b[rr] = b[rr] - l * b[c];
+      }
+    }
+    for (int rr = N - 1; rr >= 0; --rr) {
+      double s = b[rr];
+      for (int q = rr + 1; q < N; ++q) s = s - A[rr * N + q] * b[q];
+      b[rr] = s / A[rr * N + rr];
+    }
+    return true;
+  }
+
+  // Implicit leap (Rathinam et al. 2003): Newton on
+  //   F(y) = y - c - tau sum_{j noncritical} nu_j a_j(y),
+  //   c = x + sum_j nu_j (P_j - tau a_j(x)) + nu_jc [fired],
+  // with the analytic Jacobian.  Sums over reactions are scattered in
+  // ascending reaction order, so every entry receives its terms in the order
+  // of the per-entry sums of lx::Lane.
+  __device__ __noinline__ bool implicit_counts(double tau, long long* k, int jc,
+                                               const SimParams& prm) {
+    double ax[M], c[N], y[N], s[N], A[N * N], gy[M];
+    for (int j = 0; j < M; ++j) ax[j] = th[j] * g[j];
+    for (int i = 0; i < N; ++i) c[i] = (double)x[i];
+    for (int j = 0; j < M; ++j) {
+      if (!ncr[j]) continue;
+      const double d = (double)k[j] - tau * ax[j];
+      for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q)
+        c[NET::NJ_SP[q]] = c[NET::NJ_SP[q]] + (double)NET::NJ_V[q] * d;
+    }
+    if (jc >= 0)
+      for (int q = NET::NJ_PTR[jc]; q < NET::NJ_PTR[jc + 1]; ++q)
+        c[NET::NJ_SP[q]] = c[NET::NJ_SP[q]] + (double)NET::NJ_V[q];
+    for (int i = 0; i < N; ++i) y[i] = (double)x[i];
+    bool converged = false;
+    for (int it = 0; it < prm.newton_maxit; ++it) {
+      n_nit += 1;
+      for (int i = 0; i < N; ++i) s[i] = 0.0;
+      for (int q = 0; q < N * N; ++q) A[q] = 0.0;
+      for (int j = 0; j < M; ++j) {
+        if (!ncr[j]) continue;
+        const double ay = th[j] * g_large_y<NET>(j, y);
+        for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q)
+          s[NET::NJ_SP[q]] = s[NET::NJ_SP[q]] + (double)NET::NJ_V[q] * ay;
+        for (int qk = NET::RX_PTR[j]; qk < NET::RX_PTR[j + 1]; ++qk) {
+          const int kk = NET::RX_SP[qk];
+          const double d = th[j] * dg_large<NET>(j, kk, y);
+          for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q) {
+            const int i = NET::NJ_SP[q];
+            A[i * N + kk] = A[i * N + kk] + (double)NET::NJ_V[q] * d;
+          }
+        }
+      }
+      double b[N];
+      for (int i = 0; i < N; ++i) b[i] = -((y[i] - c[i]) - tau * s[i]);
+      for (int i = 0; i < N; ++i)
+        for (int kk = 0; kk < N; ++kk)
+          A[i * N + kk] = (i == kk ? 1.0 : 0.0) - tau * A[i * N + kk];
+      if (!lu_solve(A, b)) break;
+      double dmax = 0.0, ymax = 0.0;
+      for (int i = 0; i < N; ++i) {
+        y[i] = y[i] + b[i];
+        const double ad = __builtin_fabs(b[i]);
+        const double ay_ = __builtin_fabs(y[i]);
+        dmax = dmax < ad ? ad : dmax;
+        ymax = ymax < ay_ ? ay_ : ymax;
+      }
+      if (!(dmax == dmax)) break;
+      if (dmax <= prm.newton_tol * (ymax < 1.0 ? 1.0 : ymax)) {
+        converged = true;
+        break;
+      }
+    }
+    if (!converged) {
+      n_nfail += 1;
+      return false;
+    }
+    for (int j = 0; j < M; ++j) gy[j] = g_large_y<NET>(j, y);
+    for (int j = 0; j < M; ++j) {
+      if (!ncr[j]) {
+        k[j] = 0;
+        continue;
+      }
+      const double v = (tau * (th[j] * gy[j]) - tau * ax[j]) + (double)k[j];
+      double kr = __builtin_round(v);
+      if (kr < 0.0) {
+        kr = 0.0;
+        n_clip += 1;
+      }
+      if (kr > 1073741824.0) kr = 1073741824.0;
+      k[j] = (long long)kr;
+    }
+    return true;
+  }
+
+  __device__ __forceinline__ void leap_attempt(const SimParams& prm, const Key& key) {
+    const u32 ea = e;
+    e = e + 1;
+    R tau_pp = P::inf();
+    int jc = -1;
+    R uc1 = (R)0, uc2 = (R)0;
+    if (a0c > (R)0) {
+      const Words4 w = draw_block(key, pid, ea, SITE_CRIT, 0);
+      P::uniforms(w, &uc1, &uc2);
+      tau_pp = -P::ulog(uc1) / a0c;
+    }
+    R tau_r;
+    if (tau_p < tau_pp) {
+      tau_r = tau_p;
+    } else {
+      tau_r = tau_pp;
+      const R thr_ = uc2 * a0c;
+      R cum = (R)0;
+      int jlast = -1;
+      for (int j = 0; j < M; ++j) {
+        if (crit[j]) {
+          jlast = j;
+          cum = cum + a[j];
+          if (cum > thr_) {
+            jc = j;
+            break;
+          }
+        }
+      }
+      if (jc < 0) jc = jlast;
+    }
+    double tau = (double)tau_r;
+    const double rem = prm.t_end - t;
+    bool last = false;
+    if (tau >= rem) {
+      tau = rem;
+      jc = -1;
+      last = true;
+    }
+    const R tau_rr = (R)tau;
+    const R lam_thr = (R)prm.lam_thr;
+    long long k[M];
+    bool overflow = false;
+    for (int j = 0; j < M; ++j) {
+      k[j] = 0;
+      if (ncr[j]) {
+        const long long kj =
+            poisson_sample_call<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
+        overflow = overflow || kj < 0;
+        k[j] = kj;
+      }
+    }
+    if (overflow) {
+      status = LANE_LAMBDA_OVERFLOW;
+      return;
+    }
+    bool ok = true;
+    if (implicit) ok = implicit_counts(tau, k, jc, prm);
+    long long xn[N];
+    if (ok) {
+      if (jc >= 0) k[jc] = 1;
+      for (int i = 0; i < N; ++i) {
+        long long v = x[i];
+        for (int q = NET::NI_PTR[i]; q < NET::NI_PTR[i + 1]; ++q)
+          v = v + (long long)NET::NI_V[q] * k[NET::NI_RX[q]];
+        xn[i] = v;
+        ok = ok && v >= 0;
+      }
+    }
+    if (!ok) {
+      n_rej += 1;
+      tau_p = tau_p / (R)2;
+      return;
+    }
+    bool big = false;
+    for (int i = 0; i < N; ++i) big = big || xn[i] > 2147483647LL;
+    for (int j = 0; j < M; ++j) big = big || (long long)r[j] + k[j] > 2147483647LL;
+    if (big) {
+      status = LANE_COUNT_OVERFLOW;
+      return;
+    }
+    for (int i = 0; i < N; ++i) x[i] = (int)xn[i];
+    for (int j = 0; j < M; ++j) {
+      const double gn = g_large<NET>(j, x);
+      G[j] = G[j] + (tau * (g[j] + gn)) * 0.5;
+      r[j] = r[j] + (int)k[j];
+      g[j] = gn;
+    }
+    t = last ? prm.t_end : t + tau;
+    if (implicit) n_im += 1;
+    else n_ex += 1;
+    plan = false;
+    gvalid = true;
+  }
+
+  __device__ __forceinline__ void step(const SimParams& prm, const Key& key) {
+    if (!plan) propensities();
+    if (a0 == (R)0) {
+      absorb(prm);
+      return;
+    }
+    if (prm.mode != MODE_SSA && ssa_left == 0) {
+      if (!plan) make_plan(prm);
+      if (tau_p < (R)prm.k_ssa / a0 || a0c >= a0 / (R)prm.k_crit)
+        ssa_left = implicit ? prm.n_ssa_im : prm.n_ssa_ex;
+    }
+    if ((long long)e >= prm.max_steps) {
+      status = LANE_STEP_BUDGET;
+      return;
+    }
+    if (prm.mode == MODE_SSA || ssa_left > 0) {
+      ssa_step(prm, key);
+      if (ssa_left > 0) ssa_left -= 1;
+      plan = false;
+      return;
+    }
+    leap_attempt(prm, key);
+  }
+
+  __device__ __forceinline__ bool in_ssa(const SimParams& prm) const {
+    return prm.mode == MODE_SSA || ssa_left > 0;
+  }
+
+  __device__ __forceinline__ void ssa_burst(const SimParams& prm, const Key& key, int kmax) {
+    for (int kk = 0; kk < kmax; ++kk) {
+      if (!(active(prm) && in_ssa(prm))) break;
+      propensities();
+      if (a0 == (R)0) {
+        absorb(prm);
+        break;
+      }
+      if ((long long)e >= prm.max_steps) {
+        status = LANE_STEP_BUDGET;
+        break;
+      }
+      ssa_step(prm, key);
+      if (ssa_left > 0) ssa_left -= 1;
+      plan = false;
+    }
+  }
+};
+
+// Batched schedule for large networks: block-owned particle ranges refilled
+// from an LDS cursor, SSA bursts of up to ssa_k steps per leap iteration.
+template <class NET>
+__device__ __forceinline__ void run_large(long long blk, const double* __restrict__ theta,
+                                          const int* __restrict__ x0, int* x_out, int* r_out,
+                                          double* G_out, Stats* stats, const SimParams& prm,
+                                          unsigned long long* next) {
+  const int lane_id = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int waves = blockDim.x >> 6;
+  const long long lo = blk * prm.per_block;
+  long long hi = lo + prm.per_block;
+  if (hi > prm.P) hi = prm.P;
+  if (threadIdx.x == 0) *next = (unsigned long long)(lo + (long long)waves * prm.lanes);
+  __syncthreads();
+  const Key key{prm.k0, prm.k1};
+  long long p = lo + (long long)wave * prm.lanes + lane_id;
+  bool has = lane_id < prm.lanes && p < hi;
+  LaneL<LX_POLICY, NET> lane;
+  if (has) lane.load(p, theta, x0, r_out, G_out, prm);
+  while (has) {
+    if (lane.active(prm)) {
+      lane.ssa_burst(prm, key, prm.ssa_k);
+      if (lane.active(prm) && !lane.in_ssa(prm)) lane.step(prm, key);
+    }
+    if (!lane.active(prm)) {
+      lane.store(p, x_out, r_out, G_out, stats);
+      p = (long long)atomicAdd(next, 1ull);
+      has = p < hi;
+      if (has) lane.load(p, theta, x0, r_out, G_out, prm);
+    }
+  }
+}
+}  // namespace lx
+
+#ifdef LX_LARGE
+extern "C" __global__ void __launch_bounds__(LX_BLOCK)
+    lx_sim_large(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
+                 int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
+  __shared__ unsigned long long next;
+  lx::run_large<LxNet>(blockIdx.x, theta, x0, x_out, r_out, G_out, stats, prm, &next);
+}
+#endif
+
+#if defined(LX_HOOKS) && defined(LX_LARGE)
+// Step decision on fixed states (test hook); crit/eq as ceil(M/32) mask words per case.
+extern "C" __global__ void __launch_bounds__(64)
+    lx_hook_tau(const double* __restrict__ theta, const int* __restrict__ xs, double* a_out,
+                unsigned int* crit_out, unsigned int* eq_out, double* tau_out, int* action,
+                lx::SimParams prm) {
+  typedef LX_POLICY::R R;
+  constexpr int M = LxNet::M;
+  constexpr int W = (M + 31) / 32;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= prm.P) return;
+  lx::LaneL<LX_POLICY, LxNet> lane;
+  lx::SimParams p2 = prm;
+  p2.accumulate = 0;
+  p2.pid_base = 0;
+  lane.load(q, theta, xs, nullptr, nullptr, p2);
+  lane.propensities();
+  R tau_ex, tau_im;
+  lane.decide(prm, &tau_ex, &tau_im);
+  for (int j = 0; j < M; ++j) a_out[q * M + j] = (double)lane.a[j];
+  for (int w = 0; w < W; ++w) {
+    unsigned int cm = 0, em = 0;
+    for (int b = 0; b < 32 && 32 * w + b < M; ++b) {
+      cm |= (unsigned int)lane.crit[32 * w + b] << b;
+      em |= (unsigned int)lane.eq[32 * w + b] << b;
+    }
+    crit_out[q * W + w] = cm;
+    eq_out[q * W + w] = em;
+  }
+  tau_out[2 * q] = (double)tau_ex;
+  tau_out[2 * q + 1] = (double)tau_im;
+  int act;
+  if (lane.a0 == (R)0) act = 3;
+  else if (lane.tau_p < (R)prm.k_ssa / lane.a0 || lane.a0c >= lane.a0 / (R)prm.k_crit) act = 2;
+  else act = lane.implicit ? 1 : 0;
+  action[q] = act;
+}
+
+// Implicit-leap solve on fixed states (test hook).
+extern "C" __global__ void __launch_bounds__(64)
+    lx_hook_implicit(const double* __restrict__ theta, const int* __restrict__ xs,
+                     const double* __restrict__ tau, const long long* __restrict__ Pj,
+                     const int* __restrict__ jc, long long* k_out, int* ok_out, int* it_out,
+                     lx::SimParams prm) {
+  constexpr int M = LxNet::M;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= prm.P) return;
+  lx::LaneL<lx::F64, LxNet> lane;
+  lx::SimParams p2 = prm;
+  p2.accumulate = 0;
+  p2.pid_base = 0;
+  lane.load(q, theta, xs, nullptr, nullptr, p2);
+  lane.propensities();
+  for (int j = 0; j < M; ++j) lane.ncr[j] = (lane.a[j] > 0.0 && j != jc[q]) ? 1 : 0;
+  long long k[M];
+  for (int j = 0; j < M; ++j) k[j] = Pj[q * M + j];
+  const bool ok = lane.implicit_counts(tau[q], k, jc[q], prm);
+  for (int j = 0; j < M; ++j) k_out[q * M + j] = ok ? k[j] : 0;
+  ok_out[q] = ok ? 1 : 0;
+  it_out[q] = (int)lane.n_nit;
+}
+#endif

@@ -446,8 +446,9 @@ def test_tau_select(net: Network, theta, x, eps=0.03, mode="adaptive", device="c
     th = np.broadcast_to(np.asarray(theta, np.float64).reshape(-1, net.M), (Q, net.M))
     tt, xt = _t(th, torch.float64, device), _t(x, torch.int32, device)
     a = torch.empty((Q, net.M), dtype=torch.float64, device=device)
-    crit = torch.empty(Q, dtype=torch.int32, device=device)
-    eq = torch.empty(Q, dtype=torch.int32, device=device)
+    W = (net.M + 31) // 32  # mask words per case
+    crit = torch.empty((Q, W), dtype=torch.int32, device=device)
+    eq = torch.empty((Q, W), dtype=torch.int32, device=device)
     tau = torch.empty((Q, 2), dtype=torch.float64, device=device)
     act = torch.empty(Q, dtype=torch.int32, device=device)
     o = options(**opts)
@@ -455,7 +456,8 @@ def test_tau_select(net: Network, theta, x, eps=0.03, mode="adaptive", device="c
                                     MODES.get(mode, mode), C.byref(o), _ptr(a), _ptr(crit),
                                     _ptr(eq), _ptr(tau), _ptr(act), _stream_ptr(None)),
            "lx_test_tau_select")
-    bits = lambda m: ((m.cpu().numpy().view(np.uint32)[:, None] >> np.arange(net.M)) & 1).astype(np.int32)
+    bits = lambda m: ((m.cpu().numpy().view(np.uint32)[:, :, None] >> np.arange(32, dtype=np.uint32))
+                      & 1).reshape(Q, W * 32)[:, :net.M].astype(np.int32)
     return {"a": a.cpu().numpy(), "crit": bits(crit), "eq": bits(eq),
             "tau_ex": tau[:, 0].cpu().numpy(), "tau_im": tau[:, 1].cpu().numpy(),
             "action": act.cpu().numpy()}

@@ -167,6 +167,27 @@ def random_network(seed=4, N=48, M=128, n_pairs=32, frac_uni=0.4, omega=100.0,
 # Ensembles: per-particle parameters and initial states.
 # --------------------------------------------------------------------------
 
+def stiff_padded(n_pad=45, k_birth=10.0, k_death=0.1, x_pad=100) -> Network:
+    """The stiff decaying-dimerizing set plus ``n_pad`` independent birth-death
+    species (0 -> X_k, X_k -> 0): 3 + n_pad species, 4 + 2 n_pad reactions.
+
+    The slow birth-death channels bound the implicit step, the fast pair does
+    not, so implicit leaps occur; with n_pad = 45 the Newton system is 48 x 48.
+    """
+    base = dimer_stiff()
+    N, M = 3 + n_pad, 4 + 2 * n_pad
+    m = np.zeros((M, N), np.int32)
+    p = np.zeros((M, N), np.int32)
+    m[:4, :3] = base.m
+    p[:4, :3] = base.p
+    for k in range(n_pad):
+        p[4 + 2 * k, 3 + k] = 1      # 0 -> X_k
+        m[5 + 2 * k, 3 + k] = 1      # X_k -> 0
+    theta = np.concatenate([base.theta, np.tile([k_birth, k_death], n_pad)])
+    x0 = np.concatenate([base.x0, np.full(n_pad, x_pad)])
+    return _net(f"stiff_padded{n_pad}", m, p, theta, x0)
+
+
 def tile(net: Network, P: int):
     """Every particle gets the nominal theta and x0: theta [P][M], x0 [P][N]."""
     theta = np.ascontiguousarray(np.broadcast_to(net.theta, (P, net.M)), dtype=np.float64)

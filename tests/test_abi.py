@@ -63,7 +63,12 @@ def test_network_validation():
     assert _create([[2, 2]], [[0, 0]])[0] == -1      # order 4 across species
     assert _create([[-1]], [[0]])[0] == -1           # negative entry
     assert _create([[1]], [[-2]])[0] == -1
-    assert _create(np.zeros((33, 1)), np.ones((33, 1)))[0] == -1   # M above 32
+    assert _create(np.zeros((257, 1)), np.ones((257, 1)))[0] == -1   # M above 256
+    assert _create(np.zeros((1, 65)), np.ones((1, 65)))[0] == -1     # N above 64
+    for shape in ((33, 1), (4, 17), (128, 48)):  # large-network kernels
+        rc, h = _create(np.zeros(shape), np.ones(shape))
+        assert rc == 0
+        assert L.lx_network_destroy(h) == 0
     rc, h = _create(W.dimer().m, W.dimer().p)
     assert rc == 0
     n, m, q = C.c_int32(), C.c_int32(), C.c_int32()

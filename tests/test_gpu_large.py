@@ -1,0 +1,159 @@
+"""Networks beyond the register-resident kernels (lx_sim_large): the random
+48 x 128 mass-action network and a 48-species stiff network whose implicit
+leaps solve a 48 x 48 Newton system.
+
+The large-network kernels perform the operations of the oracle in the same
+order, so results are compared exactly, as for the small networks: whole
+simulations element by element (X, r, G and every lane statistic), the step
+decision (propensities, critical and equilibrium sets over four mask words,
+tau) and the implicit solve on fixed states; at the full size of the random
+network's workload (65536 trajectories, t_end 10) on sampled trajectories.
+"""
+
+import numpy as np
+import pytest
+
+from paper_1608_07058_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lxm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_07058_amd import lx
+    lx.lib()
+    return lx
+
+
+_H = {}
+
+
+def _handle(lxm, net):
+    if net.name not in _H:
+        _H[net.name] = lxm.Network(net.m, net.p)
+    return _H[net.name]
+
+
+def _gpu(lxm, net, theta, x0, t_end, mode, **opts):
+    import torch
+    th = torch.as_tensor(np.ascontiguousarray(theta, np.float64), device="cuda")
+    xi = torch.as_tensor(np.ascontiguousarray(x0, np.int32), device="cuda")
+    res = lxm.simulate(_handle(lxm, net), th, xi, t_end, 0.03, mode, **opts)
+    torch.cuda.synchronize()
+    return {"x": res["x"].cpu().numpy(), "r": res["r"].cpu().numpy(),
+            "G": res["G"].cpu().numpy(), "stats": lxm.stats_numpy(res["stats"])}
+
+
+def _same(got, ref, what):
+    for k in ("x", "r", "G"):
+        assert np.array_equal(got[k], ref[k]), (what, k)
+    for k in ref["stats"].dtype.names:
+        if k in ("pad", "ops"):
+            continue
+        assert np.array_equal(got["stats"][k], ref["stats"][k]), (what, k)
+
+
+RANDOM = W.random_network()
+STIFF = W.stiff_padded()
+
+
+def _random_inputs(P):
+    wl = W.random_network_workload(P=P)
+    return wl.theta[0], wl.x0[0]
+
+
+_REF = {}
+
+
+@pytest.mark.parametrize("schedule", ["plain", "batched"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_random_network_elementwise(lxm, orc, precision, schedule):
+    # 300 trajectories: several waves and a ragged tail; to t_end 0.2 a
+    # trajectory takes ~4000 leaps, then SSA bursts (~20000 steps).
+    net = RANDOM
+    theta, x0 = _random_inputs(300)
+    got = _gpu(lxm, net, theta, x0, 0.2, "adaptive", precision=precision, schedule=schedule)
+    if precision not in _REF:
+        _REF[precision] = orc.simulate(net.m, net.p, theta, x0, 0.2, mode="adaptive",
+                                       precision=precision)
+    _same(got, _REF[precision], f"random/{precision}/{schedule}")
+    assert got["stats"]["steps_explicit"].sum() > 0 and got["stats"]["steps_ssa"].sum() > 0
+
+
+@pytest.mark.parametrize("mode", ["adaptive", "explicit", "ssa"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_stiff_padded_elementwise(lxm, orc, precision, mode):
+    net = STIFF
+    P = 200
+    theta, x0 = W.tile(net, P)
+    theta = theta * np.random.default_rng(7).gamma(4.0, 0.25, size=theta.shape)
+    t_end = 0.05 if mode == "ssa" else 0.5
+    got = _gpu(lxm, net, theta, x0, t_end, mode, precision=precision, schedule="batched",
+               lanes_per_wave=32, ssa_k=3)
+    ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode=mode, precision=precision)
+    _same(got, ref, f"stiff/{precision}/{mode}")
+    if mode == "adaptive":
+        assert got["stats"]["steps_implicit"].sum() > 0
+        assert got["stats"]["newton_iters"].sum() > 0
+
+
+def _states(net, Q, rng):
+    scale = np.maximum(net.x0, 50)
+    x = rng.integers(0, 3 * scale + 1, size=(Q, net.N))
+    x[: Q // 4] = rng.integers(0, 12, size=(Q // 4, net.N))
+    th = net.theta * rng.gamma(2.0, 0.5, size=(Q, net.M))
+    return x.astype(np.int32), th
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["random", "stiff"])
+def test_step_decision_bit_exact(lxm, orc, name, precision):
+    net = RANDOM if name == "random" else STIFF
+    rng = np.random.default_rng(5)
+    x, th = _states(net, 1000, rng)
+    if name == "stiff":  # reversible pair near balance: equilibrium sets
+        x[::2, 1] = np.maximum(1, (th[::2, 1] * x[::2, 0] * (x[::2, 0] - 1) / 2 / th[::2, 2]).astype(np.int64)).clip(max=2**30)
+    got = lxm.test_tau_select(_handle(lxm, net), th, x, 0.03, "adaptive", precision=precision)
+    ref = orc.tau_select(net.m, net.p, th, x, mode="adaptive", precision=precision)
+    for k in ("a", "crit", "eq", "tau_ex", "tau_im", "action"):
+        assert np.array_equal(got[k], ref[k]), k
+    if name == "stiff":
+        assert ref["eq"].any()
+
+
+def test_implicit_solve_48_bit_exact(lxm, orc):
+    net = STIFF
+    assert net.N == 48
+    rng = np.random.default_rng(9)
+    Q = 500
+    x, th = _states(net, Q, rng)
+    x = np.maximum(x, 1)
+    tau = rng.uniform(1e-4, 0.5, Q)
+    res = orc.tau_select(net.m, net.p, th, x)
+    Pj = rng.poisson(np.minimum(res["a"] * tau[:, None], 1e6))
+    jc = np.where(rng.uniform(size=Q) < 0.3, rng.integers(0, net.M, Q), -1).astype(np.int32)
+    got = lxm.test_implicit(_handle(lxm, net), th, x, tau, Pj, jc)
+    ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc)
+    assert np.array_equal(got["ok"], ref["ok"])
+    assert np.array_equal(got["iters"], ref["iters"])
+    assert np.array_equal(got["k"], ref["k"])
+    assert got["ok"].mean() > 0.5
+
+
+def test_large_network_limits(lxm):
+    m = np.zeros((257, 2), np.int32)
+    with pytest.raises(lxm.LxError):
+        lxm.Network(m, m)
+    m = np.zeros((4, 65), np.int32)
+    with pytest.raises(lxm.LxError):
+        lxm.Network(m, m)
+    import torch
+    theta, x0 = _random_inputs(64)
+    th = torch.as_tensor(theta, device="cuda")
+    xi = torch.as_tensor(x0, device="cuda")
+    for bad in (dict(lanes_per_traj=4), dict(regroup=2)):
+        with pytest.raises(lxm.LxError):
+            lxm.simulate(_handle(lxm, RANDOM), th, xi, 0.01, schedule="batched", **bad)
