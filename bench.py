@@ -29,6 +29,9 @@ METRIC = "trajectories/s and reaction-events/s on 1 GPU, batched-mixed vs plain 
 # VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
 # (one fp64 or fp32 add/mul/fma, or one integer operation, per lane per cycle).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Device sources compiled into the simulation kernels at run time.
+KERNEL_SOURCES = ("lx_params.h", "lx_device.h", "lx_sim.h")
+PROFILES = os.path.join(ROOT, "profiles")
 FORMS = {
     "plain_fp64": {"precision": "fp64", "schedule": "plain"},
     "plain_mixed": {"precision": "mixed", "schedule": "plain"},
@@ -65,6 +68,36 @@ def copy_calibration(args):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": n * 4, "copies": args.steps}), flush=True)
+
+
+def kernel_id(opts):
+    """Hash of the kernel sources and the launch options of one form: HBM traffic
+    measured with hardware counters is reported only for the kernel it was
+    measured on."""
+    import hashlib
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1608_07058_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    h.update(json.dumps(opts, sort_keys=True).encode())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kid):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) recorded
+    in a profile summary for this kernel id, or None."""
+    if not os.path.isdir(PROFILES):
+        return None
+    for name in sorted(os.listdir(PROFILES)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(PROFILES, name)) as f:
+            for line in f:
+                if line.startswith("<!-- traffic ") and line.rstrip().endswith("-->"):
+                    rec = json.loads(line.strip()[len("<!-- traffic "):-len("-->")])
+                    if rec.get("kernel_id") == kid:
+                        return rec["fetch_bytes"] + rec["write_bytes"], name
+    return None
 
 
 def log(args, *a):
@@ -104,6 +137,7 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
     r_total = int(out["r"].sum(dtype=torch.int64).item())
     stats = lx.stats_numpy(out["stats"])
     return {
+        "kernel_id": kernel_id(opts),
         "ms_per_step": ms,
         "wall_s": wall,
         "trajectories_per_s": wl.P / (ms / 1e3),
@@ -175,9 +209,14 @@ def main():
     roof = None
     if ops_per_traj is not None:
         achieved = ops_per_traj * wl.P / (hr["ms_per_step"] / 1e3) / 1e12
+        rec = recorded_traffic(hr["kernel_id"])
         roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                "ops_per_trajectory": ops_per_traj, "kernel": "lx_sim_" + hr["schedule"]}
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": rec[0] if rec else None,
+                "traffic_unit": "bytes per launch", "traffic_source": rec[1] if rec else None,
+                "algorithmic_bytes": wl.P * (net.M * 8 + net.N * 4 + net.N * 4 + net.M * 4
+                                             + net.M * 8 + lx.STATS_WORDS * 8),
+                "ops_per_trajectory": ops_per_traj, "kernel": "lx_sim_" + hr["schedule"],
+                "kernel_id": hr["kernel_id"]}
     dtype = "f32+f64" if hr["precision"] == "mixed" else "f64"
     line = {
         "metric": METRIC,
