@@ -94,7 +94,7 @@ typedef struct lx_options {
   double k_crit;        /* SSA burst if a0c >= a0 / k_crit    default 10 */
   int32_t n_ssa_ex;     /* SSA burst length after an explicit choice, default 100 */
   int32_t n_ssa_im;     /* SSA burst length after an implicit choice, default 10 */
-  double lambda_thr;    /* Poisson inversion below, PTRS above, default 10, in [1,30] */
+  double lambda_thr;    /* Poisson inversion below, PTRS above, default 30, in [1,30] */
   double newton_tol;    /* Newton stop: |dy|inf <= tol*max(1,|y|inf), default 1e-10 */
   int32_t newton_maxit; /* default 20 */
   int32_t block_size;   /* threads per block (64..256, multiple of 64); 0 = default 64 */

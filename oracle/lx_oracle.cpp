@@ -368,7 +368,10 @@ void ptrs_log_density(typename P::R kf, typename P::R lam, typename P::R* lhs_fa
 
 // ---------------------------------------------------------------------------
 // Poisson sampler (Poisson leaping, Background section).
-//   lambda < lam_thr: sequential-search inversion of the CDF, one uniform.
+//   lambda < lam_thr: sequential-search inversion of the CDF, one uniform;
+//     the search stops where adding the next term no longer changes the
+//     summed CDF (the tail is below the precision's resolution; without this
+//     a uniform above the rounded CDF's ceiling would run to the cap).
 //   lambda >= lam_thr: PTRS, transformed rejection with squeeze
 //     (Hoermann 1993, "The transformed rejection method for generating
 //     Poisson random variables"), one (U, V) candidate per trial, all in the
@@ -394,8 +397,10 @@ int64_t poisson_sample(typename P::R lam, typename P::R lam_thr, int kcap, const
     while (u > F && k < kcap) {
       k = k + 1;
       p = (p * lam) / (R)k;
-      F = F + p;
-      count_ops(5);
+      const R Fn = F + p;
+      count_ops(6);
+      if (Fn == F) break;
+      F = Fn;
     }
     return k;
   }
@@ -1105,7 +1110,7 @@ void orc_default_options(orc_options* o) {
   o->n_stiff = 100.0;
   o->k_ssa = 10.0;
   o->k_crit = 10.0;
-  o->lambda_thr = 10.0;
+  o->lambda_thr = 30.0;
   o->newton_tol = 1e-10;
   o->t_start = 0.0;
   o->max_steps = 10000000;

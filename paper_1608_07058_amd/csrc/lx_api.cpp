@@ -558,7 +558,7 @@ void lx_options_default(lx_options* o) {
   o->k_crit = 10.0;
   o->n_ssa_ex = 100;
   o->n_ssa_im = 10;
-  o->lambda_thr = 10.0;
+  o->lambda_thr = 30.0;
   o->newton_tol = 1e-10;
   o->newton_maxit = 20;
   o->max_steps = 10000000;

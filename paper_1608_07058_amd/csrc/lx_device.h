@@ -353,7 +353,9 @@ __device__ __forceinline__ long long poisson_sample(typename P::R lam, typename 
     while (u > F && k < kcap) {
       k = k + 1;
       p = (p * lam) / (R)k;
-      F = F + p;
+      const R Fn = F + p;
+      if (Fn == F) break;  // the rest of the tail is below the CDF's resolution
+      F = Fn;
     }
     return k;
   }

@@ -51,8 +51,13 @@ struct LaneL {
   static constexpr int N = NET::N;
   static constexpr int M = NET::M;
 
+  static constexpr int W = (M + 31) / 32;  // mask words
+
+  // Hot per-lane state (~3.4 KB at M = 128, N = 48 in binary32): g_j is
+  // recomputed from x where needed and theta is re-read from the input row
+  // by the implicit solve, so neither is stored.
   u32 pid;
-  double th[M];
+  const double* th;  // this trajectory's theta row [M]
   R thr[M];
   int x[N];
   int r[M];
@@ -60,11 +65,10 @@ struct LaneL {
   double t;
   u32 e;
   int status;
-  double g[M];
   R a[M];
   R a0, a0c;
-  unsigned char crit[M], ncr[M], eq[M];
-  bool plan, gvalid, implicit, any_eq;
+  u32 critw[W], ncrw[W], eqw[W];  // reaction sets, bit j % 32 of word j / 32
+  bool plan, implicit, any_eq;
   R tau_p;
   int ssa_left;
   u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip;
@@ -74,15 +78,24 @@ struct LaneL {
     return status == LANE_OK && t < prm.t_end;
   }
 
+  __device__ static __forceinline__ bool bit(const u32* w, int j) {
+    return ((w[j >> 5] >> (j & 31)) & 1u) != 0u;
+  }
+  __device__ static __forceinline__ void set_bit(u32* w, int j) { w[j >> 5] |= 1u << (j & 31); }
+  __device__ __forceinline__ bool crit_(int j) const { return bit(critw, j); }
+  __device__ __forceinline__ bool ncr_(int j) const { return bit(ncrw, j); }
+  __device__ __forceinline__ bool eq_(int j) const { return bit(eqw, j); }
+
   __device__ __forceinline__ void load(long long p, const double* __restrict__ theta,
                                        const int* __restrict__ x0, const int* r_in,
                                        const double* G_in, const SimParams& prm) {
     pid = prm.pid_base + (u32)p * prm.pid_stride;
+    th = theta + p * M;
     bool bad = false;
     for (int j = 0; j < M; ++j) {
-      th[j] = theta[p * M + j];
-      thr[j] = (R)th[j];
-      bad = bad || !(th[j] >= 0.0) || th[j] == LX_INF_F64;
+      const double tj = th[j];
+      thr[j] = (R)tj;
+      bad = bad || !(tj >= 0.0) || tj == LX_INF_F64;
       r[j] = prm.accumulate ? r_in[p * M + j] : 0;
       G[j] = prm.accumulate ? G_in[p * M + j] : 0.0;
     }
@@ -94,7 +107,6 @@ struct LaneL {
     t = prm.t_start;
     e = 0;
     plan = false;
-    gvalid = false;
     implicit = false;
     ssa_left = 0;
     n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = 0;
@@ -126,14 +138,11 @@ struct LaneL {
 
   // a_j = theta_j g_j (Background section); a0 summed in ascending j.
   __device__ __forceinline__ void propensities() {
-    const bool fresh = !gvalid;
     a0 = (R)0;
     for (int j = 0; j < M; ++j) {
-      if (fresh) g[j] = g_large<NET>(j, x);
-      a[j] = thr[j] * (R)g[j];
+      a[j] = thr[j] * (R)g_large<NET>(j, x);
       a0 = a0 + a[j];
     }
-    gvalid = true;
   }
 
   __device__ __forceinline__ R phi(int i) const {
@@ -158,7 +167,7 @@ struct LaneL {
       for (int q = NET::NI_PTR[i]; q < NET::NI_PTR[i + 1]; ++q) {
         const int j = NET::NI_RX[q];
         const int v = NET::NI_V[q];
-        if (ncr[j] && !(skip_eq && eq[j])) {
+        if (ncr_(j) && !(skip_eq && eq_(j))) {
           mu = mu + (R)v * a[j];
           s2 = s2 + (R)(v * v) * a[j];
         }
@@ -176,6 +185,7 @@ struct LaneL {
 
   __device__ __forceinline__ void decide(const SimParams& prm, R* tau_ex_out, R* tau_im_out) {
     a0c = (R)0;
+    for (int w = 0; w < W; ++w) critw[w] = ncrw[w] = eqw[w] = 0u;
     for (int j = 0; j < M; ++j) {
       int L = 0x7fffffff;
       for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q) {
@@ -187,9 +197,8 @@ struct LaneL {
       }
       const bool pos = a[j] > (R)0;
       const bool c = pos && L < prm.n_c;
-      crit[j] = c ? 1 : 0;
-      ncr[j] = (pos && !c) ? 1 : 0;
-      eq[j] = 0;
+      if (c) set_bit(critw, j);
+      if (pos && !c) set_bit(ncrw, j);
       if (c) a0c = a0c + a[j];
     }
     const R eps = (R)prm.eps;
@@ -204,11 +213,11 @@ struct LaneL {
       for (int j = 0; j < M; ++j) {
         const int k = NET::PARTNER[j];
         if (k <= j) continue;
-        if (ncr[j] && ncr[k]) {
+        if (ncr_(j) && ncr_(k)) {
           const R lo = a[k] < a[j] ? a[k] : a[j];
           if (P::fabs_(a[j] - a[k]) <= delta * lo) {
-            eq[j] = 1;
-            eq[k] = 1;
+            set_bit(eqw, j);
+            set_bit(eqw, k);
             any_eq = true;
           }
         }
@@ -232,7 +241,7 @@ struct LaneL {
 
   __device__ __forceinline__ void absorb(const SimParams& prm) {
     const double rem = prm.t_end - t;
-    for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * rem;
+    for (int j = 0; j < M; ++j) G[j] = G[j] + g_large<NET>(j, x) * rem;
     t = prm.t_end;
   }
 
@@ -262,11 +271,10 @@ struct LaneL {
       }
     }
     if (jf < 0) jf = jlast;
-    for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * tau_s;
+    for (int j = 0; j < M; ++j) G[j] = G[j] + g_large<NET>(j, x) * tau_s;
     for (int q = NET::NJ_PTR[jf]; q < NET::NJ_PTR[jf + 1]; ++q) x[NET::NJ_SP[q]] += NET::NJ_V[q];
     r[jf] = r[jf] + 1;
     t = t + tau_s;
-    gvalid = false;
   }
 
   // Dense LU with partial pivoting (first maximal pivot); A row-major N x N.
@@ -312,13 +320,12 @@ struct LaneL {
   // with the analytic Jacobian.  Sums over reactions are scattered in
   // ascending reaction order, so every entry receives its terms in the order
   // of the per-entry sums of lx::Lane.
-  __device__ __noinline__ bool implicit_counts(double tau, long long* k, int jc,
-                                               const SimParams& prm) {
+  __device__ __noinline__ bool implicit_counts(double tau, int* k, int jc, const SimParams& prm) {
     double ax[M], c[N], y[N], s[N], A[N * N], gy[M];
-    for (int j = 0; j < M; ++j) ax[j] = th[j] * g[j];
+    for (int j = 0; j < M; ++j) ax[j] = th[j] * g_large<NET>(j, x);
     for (int i = 0; i < N; ++i) c[i] = (double)x[i];
     for (int j = 0; j < M; ++j) {
-      if (!ncr[j]) continue;
+      if (!ncr_(j)) continue;
       const double d = (double)k[j] - tau * ax[j];
       for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q)
         c[NET::NJ_SP[q]] = c[NET::NJ_SP[q]] + (double)NET::NJ_V[q] * d;
@@ -333,7 +340,7 @@ struct LaneL {
       for (int i = 0; i < N; ++i) s[i] = 0.0;
       for (int q = 0; q < N * N; ++q) A[q] = 0.0;
       for (int j = 0; j < M; ++j) {
-        if (!ncr[j]) continue;
+        if (!ncr_(j)) continue;
         const double ay = th[j] * g_large_y<NET>(j, y);
         for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q)
           s[NET::NJ_SP[q]] = s[NET::NJ_SP[q]] + (double)NET::NJ_V[q] * ay;
@@ -372,7 +379,7 @@ struct LaneL {
     }
     for (int j = 0; j < M; ++j) gy[j] = g_large_y<NET>(j, y);
     for (int j = 0; j < M; ++j) {
-      if (!ncr[j]) {
+      if (!ncr_(j)) {
         k[j] = 0;
         continue;
       }
@@ -383,7 +390,7 @@ struct LaneL {
         n_clip += 1;
       }
       if (kr > 1073741824.0) kr = 1073741824.0;
-      k[j] = (long long)kr;
+      k[j] = (int)kr;
     }
     return true;
   }
@@ -408,7 +415,7 @@ struct LaneL {
       R cum = (R)0;
       int jlast = -1;
       for (int j = 0; j < M; ++j) {
-        if (crit[j]) {
+        if (crit_(j)) {
           jlast = j;
           cum = cum + a[j];
           if (cum > thr_) {
@@ -429,15 +436,17 @@ struct LaneL {
     }
     const R tau_rr = (R)tau;
     const R lam_thr = (R)prm.lam_thr;
-    long long k[M];
+    // Counts fit int32: the samplers' means are at most 2^30 and the
+    // implicit counts are clamped there.
+    int k[M];
     bool overflow = false;
     for (int j = 0; j < M; ++j) {
       k[j] = 0;
-      if (ncr[j]) {
+      if (ncr_(j)) {
         const long long kj =
             poisson_sample_call<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
         overflow = overflow || kj < 0;
-        k[j] = kj;
+        k[j] = (int)kj;
       }
     }
     if (overflow) {
@@ -446,15 +455,17 @@ struct LaneL {
     }
     bool ok = true;
     if (implicit) ok = implicit_counts(tau, k, jc, prm);
-    long long xn[N];
+    int xn[N];
+    bool big = false;
     if (ok) {
       if (jc >= 0) k[jc] = 1;
       for (int i = 0; i < N; ++i) {
         long long v = x[i];
         for (int q = NET::NI_PTR[i]; q < NET::NI_PTR[i + 1]; ++q)
           v = v + (long long)NET::NI_V[q] * k[NET::NI_RX[q]];
-        xn[i] = v;
         ok = ok && v >= 0;
+        big = big || v > 2147483647LL;
+        xn[i] = (int)v;
       }
     }
     if (!ok) {
@@ -462,25 +473,23 @@ struct LaneL {
       tau_p = tau_p / (R)2;
       return;
     }
-    bool big = false;
-    for (int i = 0; i < N; ++i) big = big || xn[i] > 2147483647LL;
     for (int j = 0; j < M; ++j) big = big || (long long)r[j] + k[j] > 2147483647LL;
     if (big) {
       status = LANE_COUNT_OVERFLOW;
       return;
     }
-    for (int i = 0; i < N; ++i) x[i] = (int)xn[i];
+    // trapezoid with the old and the accepted state
     for (int j = 0; j < M; ++j) {
-      const double gn = g_large<NET>(j, x);
-      G[j] = G[j] + (tau * (g[j] + gn)) * 0.5;
-      r[j] = r[j] + (int)k[j];
-      g[j] = gn;
+      const double go = g_large<NET>(j, x);
+      const double gn = g_large<NET>(j, xn);
+      G[j] = G[j] + (tau * (go + gn)) * 0.5;
+      r[j] = r[j] + k[j];
     }
+    for (int i = 0; i < N; ++i) x[i] = xn[i];
     t = last ? prm.t_end : t + tau;
     if (implicit) n_im += 1;
     else n_ex += 1;
     plan = false;
-    gvalid = true;
   }
 
   __device__ __forceinline__ void step(const SimParams& prm, const Key& key) {
@@ -595,13 +604,8 @@ extern "C" __global__ void __launch_bounds__(64)
   lane.decide(prm, &tau_ex, &tau_im);
   for (int j = 0; j < M; ++j) a_out[q * M + j] = (double)lane.a[j];
   for (int w = 0; w < W; ++w) {
-    unsigned int cm = 0, em = 0;
-    for (int b = 0; b < 32 && 32 * w + b < M; ++b) {
-      cm |= (unsigned int)lane.crit[32 * w + b] << b;
-      em |= (unsigned int)lane.eq[32 * w + b] << b;
-    }
-    crit_out[q * W + w] = cm;
-    eq_out[q * W + w] = em;
+    crit_out[q * W + w] = lane.critw[w];
+    eq_out[q * W + w] = lane.eqw[w];
   }
   tau_out[2 * q] = (double)tau_ex;
   tau_out[2 * q + 1] = (double)tau_im;
@@ -627,9 +631,11 @@ extern "C" __global__ void __launch_bounds__(64)
   p2.pid_base = 0;
   lane.load(q, theta, xs, nullptr, nullptr, p2);
   lane.propensities();
-  for (int j = 0; j < M; ++j) lane.ncr[j] = (lane.a[j] > 0.0 && j != jc[q]) ? 1 : 0;
-  long long k[M];
-  for (int j = 0; j < M; ++j) k[j] = Pj[q * M + j];
+  for (int w = 0; w < lane.W; ++w) lane.ncrw[w] = 0u;
+  for (int j = 0; j < M; ++j)
+    if (lane.a[j] > 0.0 && j != jc[q]) lane.set_bit(lane.ncrw, j);
+  int k[M];
+  for (int j = 0; j < M; ++j) k[j] = (int)Pj[q * M + j];
   const bool ok = lane.implicit_counts(tau[q], k, jc[q], prm);
   for (int j = 0; j < M; ++j) k_out[q * M + j] = ok ? k[j] : 0;
   ok_out[q] = ok ? 1 : 0;

@@ -44,7 +44,7 @@ def test_struct_layouts_and_defaults():
     assert lx.STATS_DTYPE.itemsize == 80
     o = lx.options()
     assert (o.precision, o.schedule, o.n_c, o.n_ssa_ex, o.n_ssa_im, o.newton_maxit) == (0, 0, 10, 100, 10, 20)
-    assert (o.delta, o.n_stiff, o.k_ssa, o.k_crit, o.lambda_thr, o.newton_tol) == (0.05, 100.0, 10.0, 10.0, 10.0, 1e-10)
+    assert (o.delta, o.n_stiff, o.k_ssa, o.k_crit, o.lambda_thr, o.newton_tol) == (0.05, 100.0, 10.0, 10.0, 30.0, 1e-10)
     assert o.seed == 160807058 and o.max_steps == 10_000_000
 
 

@@ -181,29 +181,52 @@ def test_lfact_matches_lgamma(orc):
 # Samplers
 # ---------------------------------------------------------------------------
 
-def _site_uniform(orc, pid, e, site, trial=0, seed=SEED, stream=0):
+def _site_uniform(orc, pid, e, site, trial=0, seed=SEED, stream=0, precision="fp64"):
+    # the first uniform of the draw site: words 0-1 (binary64) or word 0 (binary32)
     n = len(pid)
     ctr = np.stack([pid, np.full(n, e), np.full(n, site), np.full(n, trial)], 1).astype(np.uint32)
     key = np.tile(np.array([seed & 0xFFFFFFFF, ((seed >> 32) + stream) & 0xFFFFFFFF], np.uint32),
                   (n, 1))
     w = orc.philox(ctr, key)
+    if precision == "mixed":
+        return orc.uniform_f32(w[:, 0]).astype(np.float64)
     return orc.uniform_f64(w[:, :2])
 
 
-@pytest.mark.parametrize("lam", [1e-6, 0.05, 0.5, 1.0, 3.0, 7.5, 9.99])
-def test_poisson_inversion_is_the_exact_quantile(orc, lam):
-    # Below the threshold the sampler must return the smallest k with u <= F(k)
-    # for the site's first uniform: scipy's exact Poisson quantile function.
+@pytest.mark.parametrize("precision,margin", [("fp64", 1e-12), ("mixed", 2e-5)])
+@pytest.mark.parametrize("lam", [1e-6, 0.05, 0.5, 1.0, 3.0, 7.5, 9.99, 12.0, 20.0, 29.9])
+def test_poisson_inversion_is_the_exact_quantile(orc, lam, precision, margin):
+    # Below the threshold (30 by default) the sampler must return the smallest
+    # k with u <= F(k) for the site's first uniform: scipy's exact Poisson
+    # quantile function, except where u lies within the rounding of the
+    # summed CDF (a few units of the policy's precision times the number of
+    # terms) of one of its steps.
     n = 20000
     pid = np.arange(n, dtype=np.uint32)
-    u = _site_uniform(orc, pid, 7, 3)
-    k = orc.poisson(np.full(n, lam), pid, 7, 3)
+    u = _site_uniform(orc, pid, 7, 3, precision=precision)
+    k = orc.poisson(np.full(n, lam), pid, 7, 3, precision=precision)
     ref = stats.poisson.ppf(u, lam)
     cdf_k = stats.poisson.cdf(ref, lam)
     cdf_km1 = stats.poisson.cdf(ref - 1, lam)
-    clear = (np.abs(u - cdf_k) > 1e-12) & (np.abs(u - cdf_km1) > 1e-12)
-    assert clear.mean() > 0.999
+    clear = (np.abs(u - cdf_k) > margin) & (np.abs(u - cdf_km1) > margin)
+    assert clear.mean() > 0.99
     assert np.array_equal(k[clear], ref[clear].astype(np.int64))
+
+
+def test_poisson_inversion_tail_stops_at_the_cdf_resolution(orc):
+    # In binary32 the summed CDF ends just below 1; a uniform above that
+    # ceiling must not run the search to the cap (20 + 4*30 = 140) but stop
+    # where the terms stop adding to the sum, deep in the tail.  The particle
+    # ids with the largest first uniforms among 2^24 are exactly such inputs.
+    n = 1 << 24
+    pid = np.arange(n, dtype=np.uint32)
+    u = _site_uniform(orc, pid, 7, 3, precision="mixed")
+    top = pid[np.argsort(u)[-64:]]
+    assert u.max() > 1.0 - 2.0 ** -22
+    for lam in (1.0, 3.0, 9.9, 20.0, 29.9):
+        k = orc.poisson(np.full(top.size, lam), top, 7, 3, precision="mixed")
+        assert k.max() < 140, lam
+        assert k.max() <= stats.poisson.ppf(1.0 - 1e-10, lam) + 10, (lam, k.max())
 
 
 def _chi2_poisson(samples, lam):
