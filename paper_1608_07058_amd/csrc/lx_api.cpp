@@ -265,9 +265,30 @@ std::string named_net(const lx_network_s& n, int k) {
   return src.replace(at, 1, std::to_string(k));
 }
 
-// Full hipRTC source of one kernel variant of a network.
+// The method constants of a launch as compile-time values (see LXP in
+// lx_params.h): one kernel per set of values; doubles in hexadecimal so the
+// constants are the exact binary64 values of the options.
+std::string const_source(const lx::SimParams& p) {
+  char buf[1024];
+  snprintf(buf, sizeof(buf),
+           "#define LX_CONST 1\n"
+           "struct LxConst {\n"
+           "  static constexpr double eps = %a, delta = %a, n_stiff = %a, k_ssa = %a, k_crit = %a,\n"
+           "      lam_thr = %a, newton_tol = %a;\n"
+           "  static constexpr long long max_steps = %lldLL;\n"
+           "  static constexpr int n_c = %d, n_ssa_ex = %d, n_ssa_im = %d, newton_maxit = %d,\n"
+           "      kcap = %d, mode = %d, accumulate = %d, ssa_k = %d, regroup = %d;\n"
+           "};\n",
+           p.eps, p.delta, p.n_stiff, p.k_ssa, p.k_crit, p.lam_thr, p.newton_tol, p.max_steps,
+           p.n_c, p.n_ssa_ex, p.n_ssa_im, p.newton_maxit, p.kcap, p.mode, p.accumulate, p.ssa_k,
+           p.regroup);
+  return buf;
+}
+
+// Full hipRTC source of one kernel variant of a network; `consts` is
+// const_source() of the launch, or empty for run-time constants (hooks).
 std::string kernel_source(const lx_network_s& net, const char* variant, int precision, int block,
-                          int tpl) {
+                          int tpl, const std::string& consts) {
   std::ostringstream src;
   src << "// generated by liblx\n";
   src << "#define LX_TPL " << tpl << "\n";
@@ -276,7 +297,7 @@ std::string kernel_source(const lx_network_s& net, const char* variant, int prec
   if (strcmp(variant, "hooks") == 0) src << "#define LX_HOOKS 1\n";
   if (strcmp(variant, "batched") == 0) src << "#define LX_BATCHED 1\n";
   if (net.large) src << "#define LX_LARGE 1\n";
-  src << lx_src_params << "\n" << lx_src_device << "\n" << named_net(net, 0)
+  src << consts << lx_src_params << "\n" << lx_src_device << "\n" << named_net(net, 0)
       << "typedef LxNet0 LxNet;\n" << lx_src_sim;
   if (net.large) src << "\n" << lx_src_sim_large;
   return src.str();
@@ -285,9 +306,9 @@ std::string kernel_source(const lx_network_s& net, const char* variant, int prec
 // hipRTC source of the multi-network kernel: every network of the set as
 // LxNet<k>, and a kernel that picks the network of its block.
 std::string set_source(const std::vector<const lx_network_s*>& nets, int precision, int block,
-                       int tpl) {
+                       int tpl, const std::string& consts) {
   std::ostringstream src;
-  src << "// generated by liblx (network set)\n";
+  src << "// generated by liblx (network set)\n" << consts;
   src << "#define LX_TPL " << tpl << "\n";
   src << "#define LX_POLICY " << (precision == LX_PREC_MIXED ? "lx::Mixed" : "lx::F64") << "\n";
   src << "#define LX_BLOCK " << block << "\n#define LX_SET 1\n";
@@ -360,12 +381,20 @@ lx_status get_kernel_src(lx_network_s* owner, const std::string& variant_key, F 
 }
 
 lx_status get_kernel(lx_network_s* net, const char* variant, int precision, int block,
-                     const char* fname, hipFunction_t* fn, int tpl = 1) {
+                     const char* fname, hipFunction_t* fn, int tpl, const std::string& consts) {
   std::ostringstream key;
-  key << variant << "/" << precision << "/" << block << "/tpl" << tpl;
-  return get_kernel_src(net, key.str(),
-                        [&]() { return kernel_source(*net, variant, precision, block, tpl); },
-                        fname, fn);
+  key << variant << "/" << precision << "/" << block << "/tpl" << tpl << "/c" << std::hex
+      << fnv1a(consts) << std::dec;
+  return get_kernel_src(
+      net, key.str(), [&]() { return kernel_source(*net, variant, precision, block, tpl, consts); },
+      fname, fn);
+}
+
+// Schedule-dependent fields of the launch parameters in canonical form (they
+// are compile-time constants of the kernel, so equal launches share it).
+void finish_params(const lx_options& o, bool batched, lx::SimParams* prm) {
+  prm->ssa_k = batched ? (o.ssa_k ? o.ssa_k : 4) : 0;
+  prm->regroup = batched ? o.regroup : 0;
 }
 
 // Active lanes per wave of the batched schedule: full waves when the ensemble
@@ -479,7 +508,9 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
     const bool batched = o.schedule == LX_SCHED_BATCHED;
     L->batched = true;
     L->block = o.block_size ? o.block_size : (batched ? 256 : 64);
-    st = get_kernel(net, "large", o.precision, L->block, "lx_sim_large", &L->fn, 1);
+    finish_params(o, true, &L->prm);
+    st = get_kernel(net, "large", o.precision, L->block, "lx_sim_large", &L->fn, 1,
+                    const_source(L->prm));
     if (st != LX_OK) return st;
     long long per_block = L->block;
     int lanes = 64;
@@ -495,17 +526,16 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
     }
     L->prm.per_block = per_block;
     L->prm.lanes = lanes;
-    L->prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
-    L->prm.regroup = 0;
     L->grid = (P + per_block - 1) / per_block;
     if (L->grid > 0x7fffffffLL) return fail(LX_E_INVALID, "P too large for one launch");
     return LX_OK;
   }
   L->batched = o.schedule == LX_SCHED_BATCHED;
   L->block = o.block_size ? o.block_size : (L->batched ? 256 : 64);
+  finish_params(o, L->batched, &L->prm);
   st = get_kernel(net, L->batched ? "batched" : "plain", o.precision, L->block,
                   L->batched ? "lx_sim_batched" : "lx_sim_plain", &L->fn,
-                  L->batched ? tpl_of(o) : 1);
+                  L->batched ? tpl_of(o) : 1, const_source(L->prm));
   if (st != LX_OK) return st;
   L->grid = (P + L->block - 1) / L->block;
   if (L->batched) {
@@ -519,8 +549,6 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
     if (per_block < round) per_block = round;
     L->prm.per_block = per_block;
     L->prm.lanes = lanes;
-    L->prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
-    L->prm.regroup = o.regroup;
     L->grid = (P + per_block - 1) / per_block;
   }
   if (L->grid > 0x7fffffffLL) return fail(LX_E_INVALID, "P too large for one launch");
@@ -653,9 +681,19 @@ lx_status lx_network_prepare(lx_network net, int32_t precision, int32_t schedule
   if (block_size != 0 && (block_size < 64 || block_size > MAX_BLOCK || block_size % 64 != 0))
     return fail(LX_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
   const int block = block_size ? block_size : (schedule == LX_SCHED_BATCHED ? 256 : 64);
+  // the kernel lx_simulate uses with default options, eps 0.03, adaptive mode
+  lx_options o;
+  lx_options_default(&o);
+  o.precision = precision;
+  o.schedule = schedule;
+  lx::SimParams prm;
+  lx_status st = fill_params(o, 1, 1.0, 0.03, LX_MODE_ADAPTIVE, &prm);
+  if (st != LX_OK) return st;
+  const bool batched = net->large || schedule == LX_SCHED_BATCHED;
+  finish_params(o, batched, &prm);
   std::vector<char> code;
   const char* variant = net->large ? "large" : (schedule == LX_SCHED_BATCHED ? "batched" : "plain");
-  return compile_source(kernel_source(*net, variant, precision, block, 1), &code);
+  return compile_source(kernel_source(*net, variant, precision, block, 1, const_source(prm)), &code);
 }
 
 lx_status lx_network_destroy(lx_network net) {
@@ -756,11 +794,12 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
     key << "/" << std::hex << fnv1a(it.net->netsrc) << std::dec;
   }
   if (begin > 0x7fffffffLL) return fail(LX_E_INVALID, "ensemble too large for one launch");
-  prm.ssa_k = o.ssa_k ? o.ssa_k : 4;
-  prm.regroup = o.regroup;
+  finish_params(o, true, &prm);
+  const std::string consts = const_source(prm);
+  key << "/c" << std::hex << fnv1a(consts) << std::dec;
   hipFunction_t fn;
   st = get_kernel_src(items[0].net, key.str(),
-                      [&]() { return set_source(nets, o.precision, block, tpl_of(o)); },
+                      [&]() { return set_source(nets, o.precision, block, tpl_of(o), consts); },
                       "lx_sim_set", &fn);
   if (st != LX_OK) return st;
   void* kargs[] = {(void*)&args, (void*)&prm};
@@ -845,7 +884,7 @@ lx_status lx_test_tau_select(lx_network net, int64_t Q, const double* theta, con
   if (!theta || !x || !a || !crit || !eq || !tau || !action)
     return fail(LX_E_INVALID, "null pointer");
   hipFunction_t fn;
-  st = get_kernel(net, "hooks", o.precision, 64, "lx_hook_tau", &fn, 1);
+  st = get_kernel(net, "hooks", o.precision, 64, "lx_hook_tau", &fn, 1, std::string());
   if (st != LX_OK) return st;
   void* args[] = {(void*)&theta, (void*)&x, (void*)&a, (void*)&crit, (void*)&eq,
                   (void*)&tau, (void*)&action, (void*)&prm};
@@ -869,7 +908,7 @@ lx_status lx_test_implicit(lx_network net, int64_t Q, const double* theta, const
   if (!theta || !x || !tau || !Pj || !jc || !k || !ok || !iters)
     return fail(LX_E_INVALID, "null pointer");
   hipFunction_t fn;
-  st = get_kernel(net, "hooks", LX_PREC_FP64, 64, "lx_hook_implicit", &fn, 1);
+  st = get_kernel(net, "hooks", LX_PREC_FP64, 64, "lx_hook_implicit", &fn, 1, std::string());
   if (st != LX_OK) return st;
   void* args[] = {(void*)&theta, (void*)&x, (void*)&tau, (void*)&Pj, (void*)&jc,
                   (void*)&k, (void*)&ok, (void*)&iters, (void*)&prm};

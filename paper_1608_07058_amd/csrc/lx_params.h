@@ -31,6 +31,17 @@ struct SimParams {
 };
 
 // Per-trajectory statistics (layout of the public lx_stats).
+// Method constants of a launch (the fields of SimParams named below).  A
+// generated kernel source may define LX_CONST together with a struct LxConst
+// holding them as compile-time values -- the host then compiles one kernel
+// per set of values, so they fold into immediates and occupy no scalar
+// registers; otherwise they are read from the launch parameters.
+#ifdef LX_CONST
+#define LXP(prm, f) (::LxConst::f)
+#else
+#define LXP(prm, f) ((prm).f)
+#endif
+
 struct Stats {
   int status, pad;
   double t_final;

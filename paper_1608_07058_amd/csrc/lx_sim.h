@@ -114,8 +114,8 @@ struct Lane {
       th[j] = theta[p * M + j];
       thr[j] = (R)th[j];
       bad = bad || !(th[j] >= 0.0) || th[j] == LX_INF_F64;
-      r[j] = prm.accumulate ? r_in[p * M + j] : 0;
-      G[j] = prm.accumulate ? G_in[p * M + j] : 0.0;
+      r[j] = LXP(prm, accumulate) ? r_in[p * M + j] : 0;
+      G[j] = LXP(prm, accumulate) ? G_in[p * M + j] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -334,21 +334,21 @@ struct Lane {
         }
       }
       const bool pos = a[j] > (R)0;
-      const bool c = pos && L < prm.n_c;
+      const bool c = pos && L < LXP(prm, n_c);
       crit |= (c ? 1u : 0u) << j;
       ncr |= ((pos && !c) ? 1u : 0u) << j;
       if (c) a0c = a0c + a[j];
     }
-    const R eps = (R)prm.eps;
+    const R eps = (R)LXP(prm, eps);
     const R tau_ex = tau_select(ncr, eps);
     implicit = false;
     tau_p = tau_ex;
     *tau_ex_out = tau_ex;
     *tau_im_out = P::inf();
     *eq_out = 0;
-    if (NET::NPAIRS > 0 && prm.mode == MODE_ADAPTIVE) {
+    if (NET::NPAIRS > 0 && LXP(prm, mode) == MODE_ADAPTIVE) {
       u32 eq = 0;
-      const R delta = (R)prm.delta;
+      const R delta = (R)LXP(prm, delta);
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         const int k = NET::PARTNER[j];
@@ -362,7 +362,7 @@ struct Lane {
       if (eq) {
         const R tau_im = tau_select(ncr & ~eq, eps);
         *tau_im_out = tau_im;
-        if (tau_im > (R)prm.n_stiff * tau_ex) {
+        if (tau_im > (R)LXP(prm, n_stiff) * tau_ex) {
           implicit = true;
           tau_p = tau_im;
         }
@@ -503,7 +503,7 @@ struct Lane {
       y[i] = (double)x[i];
     }
     bool converged = false;
-    for (int it = 0; it < prm.newton_maxit; ++it) {
+    for (int it = 0; it < LXP(prm, newton_maxit); ++it) {
       n_nit += 1;
       double ay[M], gy[M];
       g_all<NET>(y, gy);
@@ -542,7 +542,7 @@ struct Lane {
         ymax = ymax < ay_ ? ay_ : ymax;
       }
       if (!(dmax == dmax)) break;
-      if (dmax <= prm.newton_tol * (ymax < 1.0 ? 1.0 : ymax)) {
+      if (dmax <= LXP(prm, newton_tol) * (ymax < 1.0 ? 1.0 : ymax)) {
         converged = true;
         break;
       }
@@ -614,7 +614,7 @@ struct Lane {
       last = true;
     }
     const R tau_rr = (R)tau;
-    const R lam_thr = (R)prm.lam_thr;
+    const R lam_thr = (R)LXP(prm, lam_thr);
     long long k[M];
     bool overflow = false;
     if constexpr (TPL == 1) {
@@ -624,9 +624,9 @@ struct Lane {
         if ((ncr >> j) & 1u) {
           long long kj;
           if constexpr (M > 4)
-            kj = poisson_sample_call<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
+            kj = poisson_sample_call<P>(a[j] * tau_rr, lam_thr, LXP(prm, kcap), key, pid, ea, (u32)j);
           else
-            kj = poisson_sample<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
+            kj = poisson_sample<P>(a[j] * tau_rr, lam_thr, LXP(prm, kcap), key, pid, ea, (u32)j);
           overflow = overflow || kj < 0;
           k[j] = kj;
         }
@@ -648,10 +648,10 @@ struct Lane {
         long long kj = 0;
         if (nc) {
           if constexpr ((M + TPL - 1) / TPL > 4)
-            kj = poisson_sample_call<P>(aj * tau_rr, lam_thr, prm.kcap, key, pid, ea,
+            kj = poisson_sample_call<P>(aj * tau_rr, lam_thr, LXP(prm, kcap), key, pid, ea,
                                         (u32)(g * TPL + sub));
           else
-            kj = poisson_sample<P>(aj * tau_rr, lam_thr, prm.kcap, key, pid, ea,
+            kj = poisson_sample<P>(aj * tau_rr, lam_thr, LXP(prm, kcap), key, pid, ea,
                                    (u32)(g * TPL + sub));
         }
 #pragma unroll
@@ -728,16 +728,16 @@ struct Lane {
       absorb(prm);
       return;
     }
-    if (prm.mode != MODE_SSA && ssa_left == 0) {
+    if (LXP(prm, mode) != MODE_SSA && ssa_left == 0) {
       if (!plan) make_plan(prm);
-      if (tau_p < (R)prm.k_ssa / a0 || a0c >= a0 / (R)prm.k_crit)
-        ssa_left = implicit ? prm.n_ssa_im : prm.n_ssa_ex;
+      if (tau_p < (R)LXP(prm, k_ssa) / a0 || a0c >= a0 / (R)LXP(prm, k_crit))
+        ssa_left = implicit ? LXP(prm, n_ssa_im) : LXP(prm, n_ssa_ex);
     }
-    if ((long long)e >= prm.max_steps) {
+    if ((long long)e >= LXP(prm, max_steps)) {
       status = LANE_STEP_BUDGET;
       return;
     }
-    if (prm.mode == MODE_SSA || ssa_left > 0) {
+    if (LXP(prm, mode) == MODE_SSA || ssa_left > 0) {
       ssa_step(prm, key);
       if (ssa_left > 0) ssa_left -= 1;
       plan = false;
@@ -749,7 +749,7 @@ struct Lane {
   // True when the next action is an SSA step (a burst in progress, or SSA
   // mode); such a lane needs no plan.
   __device__ __forceinline__ bool in_ssa(const SimParams& prm) const {
-    return prm.mode == MODE_SSA || ssa_left > 0;
+    return LXP(prm, mode) == MODE_SSA || ssa_left > 0;
   }
 
   // An SSA step of a lane in a burst (the SSA branch of step()).
@@ -759,7 +759,7 @@ struct Lane {
       absorb(prm);
       return;
     }
-    if ((long long)e >= prm.max_steps) {
+    if ((long long)e >= LXP(prm, max_steps)) {
       status = LANE_STEP_BUDGET;
       return;
     }
@@ -793,7 +793,7 @@ struct Lane {
             propensities();
             if (a0 == (R)0) {
               absorb(prm);
-            } else if ((long long)e >= prm.max_steps) {
+            } else if ((long long)e >= LXP(prm, max_steps)) {
               status = LANE_STEP_BUDGET;
             } else {
               ssa_apply(prm, Es, u2s);
@@ -871,7 +871,7 @@ __device__ __forceinline__ void run_batched(long long blk, const double* __restr
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
   while (has) {
     if (lane.active(prm)) {
-      lane.ssa_burst(prm, key, prm.ssa_k);
+      lane.ssa_burst(prm, key, LXP(prm, ssa_k));
       if (lane.active(prm) && !lane.in_ssa(prm)) lane.step(prm, key);
     }
     if (!lane.active(prm)) {
@@ -927,7 +927,7 @@ __device__ __forceinline__ void run_regroup(long long blk, const double* __restr
     }
     if (!__syncthreads_or(has ? 1 : 0)) break;
     int cls = has ? (lane.in_ssa(prm) ? 0 : 1) : 2;
-    if (prm.regroup > 0 && iter % prm.regroup == 0) {
+    if (LXP(prm, regroup) > 0 && iter % LXP(prm, regroup) == 0) {
       const unsigned long long b0 = __ballot(cls == 0);
       const unsigned long long b1 = __ballot(cls == 1);
       if (lane_id == 0) {
@@ -956,7 +956,7 @@ __device__ __forceinline__ void run_regroup(long long blk, const double* __restr
     const bool any1 = __ballot(cls == 1) != 0ull;
     const bool run_ssa = any0 && (!any1 || (iter & 1) == 0);
     if (cls == 0 && run_ssa) {
-      for (int k = 0; k < prm.ssa_k; ++k) {
+      for (int k = 0; k < LXP(prm, ssa_k); ++k) {
         if (!(lane.active(prm) && lane.in_ssa(prm))) break;
         lane.ssa_only(prm, key);
       }
@@ -971,7 +971,7 @@ __device__ __forceinline__ void run_sched(long long blk, const double* __restric
                                           const int* __restrict__ x0, int* x_out, int* r_out,
                                           double* G_out, Stats* stats, const SimParams& prm,
                                           unsigned long long* next) {
-  if (LX_TPL == 1 && prm.regroup > 0)
+  if (LX_TPL == 1 && LXP(prm, regroup) > 0)
     run_regroup<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next);
   else run_batched<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next);
 }
@@ -1012,7 +1012,7 @@ extern "C" __global__ void __launch_bounds__(64)
   tau_out[2 * q + 1] = (double)tau_im;
   int act;
   if (lane.a0 == (R)0) act = 3;
-  else if (lane.tau_p < (R)prm.k_ssa / lane.a0 || lane.a0c >= lane.a0 / (R)prm.k_crit) act = 2;
+  else if (lane.tau_p < (R)LXP(prm, k_ssa) / lane.a0 || lane.a0c >= lane.a0 / (R)LXP(prm, k_crit)) act = 2;
   else act = lane.implicit ? 1 : 0;
   action[q] = act;
 }

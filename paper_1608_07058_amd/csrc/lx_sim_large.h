@@ -96,8 +96,8 @@ struct LaneL {
       const double tj = th[j];
       thr[j] = (R)tj;
       bad = bad || !(tj >= 0.0) || tj == LX_INF_F64;
-      r[j] = prm.accumulate ? r_in[p * M + j] : 0;
-      G[j] = prm.accumulate ? G_in[p * M + j] : 0.0;
+      r[j] = LXP(prm, accumulate) ? r_in[p * M + j] : 0;
+      G[j] = LXP(prm, accumulate) ? G_in[p * M + j] : 0.0;
     }
     for (int i = 0; i < N; ++i) {
       x[i] = x0[p * N + i];
@@ -196,20 +196,20 @@ struct LaneL {
         }
       }
       const bool pos = a[j] > (R)0;
-      const bool c = pos && L < prm.n_c;
+      const bool c = pos && L < LXP(prm, n_c);
       if (c) set_bit(critw, j);
       if (pos && !c) set_bit(ncrw, j);
       if (c) a0c = a0c + a[j];
     }
-    const R eps = (R)prm.eps;
+    const R eps = (R)LXP(prm, eps);
     const R tau_ex = tau_select(false, eps);
     implicit = false;
     tau_p = tau_ex;
     *tau_ex_out = tau_ex;
     *tau_im_out = P::inf();
     any_eq = false;
-    if (NET::NPAIRS > 0 && prm.mode == MODE_ADAPTIVE) {
-      const R delta = (R)prm.delta;
+    if (NET::NPAIRS > 0 && LXP(prm, mode) == MODE_ADAPTIVE) {
+      const R delta = (R)LXP(prm, delta);
       for (int j = 0; j < M; ++j) {
         const int k = NET::PARTNER[j];
         if (k <= j) continue;
@@ -225,7 +225,7 @@ struct LaneL {
       if (any_eq) {
         const R tau_im = tau_select(true, eps);
         *tau_im_out = tau_im;
-        if (tau_im > (R)prm.n_stiff * tau_ex) {
+        if (tau_im > (R)LXP(prm, n_stiff) * tau_ex) {
           implicit = true;
           tau_p = tau_im;
         }
@@ -335,7 +335,7 @@ struct LaneL {
         c[NET::NJ_SP[q]] = c[NET::NJ_SP[q]] + (double)NET::NJ_V[q];
     for (int i = 0; i < N; ++i) y[i] = (double)x[i];
     bool converged = false;
-    for (int it = 0; it < prm.newton_maxit; ++it) {
+    for (int it = 0; it < LXP(prm, newton_maxit); ++it) {
       n_nit += 1;
       for (int i = 0; i < N; ++i) s[i] = 0.0;
       for (int q = 0; q < N * N; ++q) A[q] = 0.0;
@@ -368,7 +368,7 @@ struct LaneL {
         ymax = ymax < ay_ ? ay_ : ymax;
       }
       if (!(dmax == dmax)) break;
-      if (dmax <= prm.newton_tol * (ymax < 1.0 ? 1.0 : ymax)) {
+      if (dmax <= LXP(prm, newton_tol) * (ymax < 1.0 ? 1.0 : ymax)) {
         converged = true;
         break;
       }
@@ -435,7 +435,7 @@ struct LaneL {
       last = true;
     }
     const R tau_rr = (R)tau;
-    const R lam_thr = (R)prm.lam_thr;
+    const R lam_thr = (R)LXP(prm, lam_thr);
     // Counts fit int32: the samplers' means are at most 2^30 and the
     // implicit counts are clamped there.
     int k[M];
@@ -444,7 +444,7 @@ struct LaneL {
       k[j] = 0;
       if (ncr_(j)) {
         const long long kj =
-            poisson_sample_call<P>(a[j] * tau_rr, lam_thr, prm.kcap, key, pid, ea, (u32)j);
+            poisson_sample_call<P>(a[j] * tau_rr, lam_thr, LXP(prm, kcap), key, pid, ea, (u32)j);
         overflow = overflow || kj < 0;
         k[j] = (int)kj;
       }
@@ -498,16 +498,16 @@ struct LaneL {
       absorb(prm);
       return;
     }
-    if (prm.mode != MODE_SSA && ssa_left == 0) {
+    if (LXP(prm, mode) != MODE_SSA && ssa_left == 0) {
       if (!plan) make_plan(prm);
-      if (tau_p < (R)prm.k_ssa / a0 || a0c >= a0 / (R)prm.k_crit)
-        ssa_left = implicit ? prm.n_ssa_im : prm.n_ssa_ex;
+      if (tau_p < (R)LXP(prm, k_ssa) / a0 || a0c >= a0 / (R)LXP(prm, k_crit))
+        ssa_left = implicit ? LXP(prm, n_ssa_im) : LXP(prm, n_ssa_ex);
     }
-    if ((long long)e >= prm.max_steps) {
+    if ((long long)e >= LXP(prm, max_steps)) {
       status = LANE_STEP_BUDGET;
       return;
     }
-    if (prm.mode == MODE_SSA || ssa_left > 0) {
+    if (LXP(prm, mode) == MODE_SSA || ssa_left > 0) {
       ssa_step(prm, key);
       if (ssa_left > 0) ssa_left -= 1;
       plan = false;
@@ -517,7 +517,7 @@ struct LaneL {
   }
 
   __device__ __forceinline__ bool in_ssa(const SimParams& prm) const {
-    return prm.mode == MODE_SSA || ssa_left > 0;
+    return LXP(prm, mode) == MODE_SSA || ssa_left > 0;
   }
 
   __device__ __forceinline__ void ssa_burst(const SimParams& prm, const Key& key, int kmax) {
@@ -528,7 +528,7 @@ struct LaneL {
         absorb(prm);
         break;
       }
-      if ((long long)e >= prm.max_steps) {
+      if ((long long)e >= LXP(prm, max_steps)) {
         status = LANE_STEP_BUDGET;
         break;
       }
@@ -561,7 +561,7 @@ __device__ __forceinline__ void run_large(long long blk, const double* __restric
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
   while (has) {
     if (lane.active(prm)) {
-      lane.ssa_burst(prm, key, prm.ssa_k);
+      lane.ssa_burst(prm, key, LXP(prm, ssa_k));
       if (lane.active(prm) && !lane.in_ssa(prm)) lane.step(prm, key);
     }
     if (!lane.active(prm)) {
@@ -611,7 +611,7 @@ extern "C" __global__ void __launch_bounds__(64)
   tau_out[2 * q + 1] = (double)tau_im;
   int act;
   if (lane.a0 == (R)0) act = 3;
-  else if (lane.tau_p < (R)prm.k_ssa / lane.a0 || lane.a0c >= lane.a0 / (R)prm.k_crit) act = 2;
+  else if (lane.tau_p < (R)LXP(prm, k_ssa) / lane.a0 || lane.a0c >= lane.a0 / (R)LXP(prm, k_crit)) act = 2;
   else act = lane.implicit ? 1 : 0;
   action[q] = act;
 }
