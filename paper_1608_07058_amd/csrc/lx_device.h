@@ -306,34 +306,91 @@ __device__ __forceinline__ void ptrs_log_density(typename P::R kf, typename P::R
   }
 }
 
+// PTRS constants of a mean (Hoermann 1993).
+template <class P>
+struct PtrsParams {
+  typename P::R lam, a, b, inv_alpha, vr;
+};
+
+template <class P>
+__device__ __forceinline__ PtrsParams<P> ptrs_params(typename P::R lam) {
+  typedef typename P::R R;
+  PtrsParams<P> c;
+  c.lam = lam;
+  const R slam = P::sqrt_(lam);
+  c.b = (R)0.931 + (R)2.53 * slam;
+  c.a = (R)-0.059 + (R)0.02483 * c.b;
+  c.inv_alpha = (R)1.1239 + (R)1.1328 / (c.b - (R)3.4);
+  c.vr = (R)0.9277 - (R)3.6224 / (c.b - (R)2);
+  return c;
+}
+
+// Candidate `slot` of the Philox block `w` (the candidate of trial t is
+// slot t mod TRIALS_PER_BLOCK of block t / TRIALS_PER_BLOCK): true with *k
+// when accepted.
+template <class P>
+__device__ __forceinline__ bool ptrs_candidate(const PtrsParams<P>& c, const Words4& w, u32 slot,
+                                               long long* k) {
+  typedef typename P::R R;
+  R u0, v;
+  P::candidate(w, slot, &u0, &v);
+  const R u = u0 - (R)0.5;
+  const R us = (R)0.5 - P::fabs_(u);
+  const R kf = P::floor_((((R)2 * c.a) / us + c.b) * u + c.lam + (R)0.43);
+  if (kf < (R)0 || (double)kf > 1073741824.0) return false;
+  if (us >= (R)0.07 && v <= c.vr) {
+    *k = (long long)kf;
+    return true;
+  }
+  if (us < (R)0.013 && v > us) return false;
+  const R hat = c.a / (us * us) + c.b;
+  R fac, rhs;
+  ptrs_log_density<P>(kf, c.lam, &fac, &rhs);
+  const R lhs = P::ulog(((v * c.inv_alpha) * fac) / hat);
+  if (lhs <= rhs) {
+    *k = (long long)kf;
+    return true;
+  }
+  return false;
+}
+
+// Trials a PTRS draw makes before giving up (then floor(lam); probability
+// below 1e-60).
+constexpr u32 PTRS_TRIALS = 64;
+
 template <class P>
 __device__ __forceinline__ long long poisson_ptrs(typename P::R lam, const Key& key, u32 pid, u32 e,
                                                   u32 site) {
-  typedef typename P::R R;
-  const R slam = P::sqrt_(lam);
-  const R b = (R)0.931 + (R)2.53 * slam;
-  const R a = (R)-0.059 + (R)0.02483 * b;
-  const R inv_alpha = (R)1.1239 + (R)1.1328 / (b - (R)3.4);
-  const R vr = (R)0.9277 - (R)3.6224 / (b - (R)2);
+  const PtrsParams<P> c = ptrs_params<P>(lam);
   Words4 w = Words4{0u, 0u, 0u, 0u};
-  for (u32 trial = 0; trial < 64; ++trial) {
+  for (u32 trial = 0; trial < PTRS_TRIALS; ++trial) {
     if (trial % P::TRIALS_PER_BLOCK == 0u)
       w = draw_block(key, pid, e, site, trial / P::TRIALS_PER_BLOCK);
-    R u0, v;
-    P::candidate(w, trial % P::TRIALS_PER_BLOCK, &u0, &v);
-    const R u = u0 - (R)0.5;
-    const R us = (R)0.5 - P::fabs_(u);
-    const R kf = P::floor_((((R)2 * a) / us + b) * u + lam + (R)0.43);
-    if (kf < (R)0 || (double)kf > 1073741824.0) continue;
-    if (us >= (R)0.07 && v <= vr) return (long long)kf;
-    if (us < (R)0.013 && v > us) continue;
-    const R hat = a / (us * us) + b;
-    R fac, rhs;
-    ptrs_log_density<P>(kf, lam, &fac, &rhs);
-    const R lhs = P::ulog(((v * inv_alpha) * fac) / hat);
-    if (lhs <= rhs) return (long long)kf;
+    long long k;
+    if (ptrs_candidate<P>(c, w, trial % P::TRIALS_PER_BLOCK, &k)) return k;
   }
   return (long long)__builtin_floor((double)lam);
+}
+
+// Inversion below the PTRS threshold (sequential search of the CDF).
+template <class P>
+__device__ __forceinline__ long long poisson_inversion(typename P::R lam, int kcap, const Key& key,
+                                                       u32 pid, u32 e, u32 site) {
+  typedef typename P::R R;
+  const Words4 w = draw_block(key, pid, e, site, 0);
+  R u, unused;
+  P::uniforms(w, &u, &unused);
+  R p = P::uexp(-lam);
+  R F = p;
+  int k = 0;
+  while (u > F && k < kcap) {
+    k = k + 1;
+    p = (p * lam) / (R)k;
+    const R Fn = F + p;
+    if (Fn == F) break;  // the rest of the tail is below the CDF's resolution
+    F = Fn;
+  }
+  return k;
 }
 
 template <class P>
@@ -343,22 +400,7 @@ __device__ __forceinline__ long long poisson_sample(typename P::R lam, typename 
   typedef typename P::R R;
   if (!(lam > (R)0)) return 0;
   if ((double)lam > P::lambda_max()) return -1;
-  if (lam < lam_thr) {
-    const Words4 w = draw_block(key, pid, e, site, 0);
-    R u, unused;
-    P::uniforms(w, &u, &unused);
-    R p = P::uexp(-lam);
-    R F = p;
-    int k = 0;
-    while (u > F && k < kcap) {
-      k = k + 1;
-      p = (p * lam) / (R)k;
-      const R Fn = F + p;
-      if (Fn == F) break;  // the rest of the tail is below the CDF's resolution
-      F = Fn;
-    }
-    return k;
-  }
+  if (lam < lam_thr) return poisson_inversion<P>(lam, kcap, key, pid, e, site);
   return poisson_ptrs<P>(lam, key, pid, e, site);
 }
 

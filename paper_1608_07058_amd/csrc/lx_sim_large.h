@@ -10,16 +10,27 @@
 //   NI_PTR[N+1], NI_RX[], NI_V[]   nonzero net changes of species i (ascending reactions)
 //   PHI[N], PARTNER[M], NPAIRS
 // Loops over species and reactions run at run time with wave-uniform trip
-// counts and table indices (scalar loads).  The per-lane arrays (theta, r, G,
-// g, a, reaction sets, counts, the Newton system) are private arrays indexed
-// at run time, which live in the private segment; it is interleaved by lane,
-// so a uniform index across a wave is one contiguous access.
+// counts and table indices (scalar loads).  The per-lane arrays (theta in the
+// policy's precision, r, G, a, Poisson counts, the Newton system) are private
+// arrays indexed at run time, which live in the private segment; it is
+// interleaved by lane, so a uniform index across a wave is one contiguous
+// access.  The species counts live in LDS; g_j is recomputed from them where
+// needed and the reaction sets are bit masks.
 #pragma once
 
 namespace lx {
 
-template <class NET>
-__device__ __forceinline__ double g_large(int j, const int* x) {
+// Species counts of one lane in LDS: element i at p[i * LX_BLOCK] (the
+// table-driven loops index them at run time; LDS answers in tens of cycles
+// where the private segment, not resident in any cache at these sizes, takes
+// a trip to memory).
+struct XSlot {
+  int* p;
+  __device__ __forceinline__ int& operator[](int i) const { return p[i * LX_BLOCK]; }
+};
+
+template <class NET, class XV>
+__device__ __forceinline__ double g_large(int j, const XV& x) {
   double gj = 1.0;
   for (int q = NET::RX_PTR[j]; q < NET::RX_PTR[j + 1]; ++q)
     gj = gj * binom_real((double)x[NET::RX_SP[q]], NET::RX_RO[q]);
@@ -59,7 +70,7 @@ struct LaneL {
   u32 pid;
   const double* th;  // this trajectory's theta row [M]
   R thr[M];
-  int x[N];
+  XSlot x;  // species counts, in LDS
   int r[M];
   double G[M];
   double t;
@@ -557,7 +568,9 @@ __device__ __forceinline__ void run_large(long long blk, const double* __restric
   const Key key{prm.k0, prm.k1};
   long long p = lo + (long long)wave * prm.lanes + lane_id;
   bool has = lane_id < prm.lanes && p < hi;
+  __shared__ int xlds[NET::N * LX_BLOCK];
   LaneL<LX_POLICY, NET> lane;
+  lane.x.p = xlds + threadIdx.x;
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
   while (has) {
     if (lane.active(prm)) {
@@ -594,7 +607,9 @@ extern "C" __global__ void __launch_bounds__(64)
   constexpr int W = (M + 31) / 32;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= prm.P) return;
+  __shared__ int xlds[LxNet::N * LX_BLOCK];
   lx::LaneL<LX_POLICY, LxNet> lane;
+  lane.x.p = xlds + threadIdx.x;
   lx::SimParams p2 = prm;
   p2.accumulate = 0;
   p2.pid_base = 0;
@@ -625,7 +640,9 @@ extern "C" __global__ void __launch_bounds__(64)
   constexpr int M = LxNet::M;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= prm.P) return;
+  __shared__ int xlds[LxNet::N * LX_BLOCK];
   lx::LaneL<lx::F64, LxNet> lane;
+  lane.x.p = xlds + threadIdx.x;
   lx::SimParams p2 = prm;
   p2.accumulate = 0;
   p2.pid_base = 0;
