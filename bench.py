@@ -32,6 +32,12 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Device sources compiled into the simulation kernels at run time.
 KERNEL_SOURCES = ("lx_params.h", "lx_device.h", "lx_sim.h")
 PROFILES = os.path.join(ROOT, "profiles")
+# Single-network workloads bench.py can time; the headline line is "dimer".
+WORKLOADS = {
+    "dimer": "dimer_workload",
+    "birth_death": "birth_death_workload",
+    "random48x128": "random_network_workload",
+}
 FORMS = {
     "plain_fp64": {"precision": "fp64", "schedule": "plain"},
     "plain_mixed": {"precision": "mixed", "schedule": "plain"},
@@ -52,6 +58,13 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--untuned", action="store_true", help="ignore autotuned batched knobs")
+    ap.add_argument("--workload", default="dimer", choices=sorted(WORKLOADS),
+                    help="dimer (the headline, default) or a secondary single-network workload")
+    ap.add_argument("--t-end", type=float, default=0.0,
+                    help="override the workload's t_end (secondary workloads only)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="trajectories the oracle baseline runs (default: all for the dimer, "
+                         "1024 otherwise)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes --steps times "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -165,7 +178,11 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
-    wl = W.dimer_workload()
+    wl = getattr(W, WORKLOADS[args.workload])()
+    if args.t_end > 0.0:
+        if args.workload == "dimer":
+            raise SystemExit("--t-end applies to secondary workloads only")
+        wl.t_end = args.t_end
     net = wl.nets[0]
     theta = torch.as_tensor(wl.theta[0], device="cuda")
     x0 = torch.as_tensor(wl.x0[0], device="cuda")
@@ -198,13 +215,15 @@ def main():
         import oracle
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
         t0 = time.perf_counter()
-        ref = oracle.simulate(net.m, net.p, wl.theta[0], wl.x0[0], wl.t_end, mode=wl.mode,
-                              nthreads=nth)
+        n_cpu = args.cpu_sample or (wl.P if args.workload == "dimer" else min(wl.P, 1024))
+        ref = oracle.simulate(net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu], wl.t_end,
+                              mode=wl.mode, nthreads=nth)
         dt = time.perf_counter() - t0
         ops_per_traj = float(ref["stats"]["ops"].mean())
-        cpu = {"value": wl.P / dt, "unit": "trajectories/s", "cores": nth, "kind": "oracle",
-               "sample": f"all {wl.P} trajectories of the workload, fp64 oracle, {nth} threads, "
-                         f"{dt:.1f} s"}
+        what = (f"all {wl.P} trajectories of the workload" if n_cpu == wl.P else
+                f"the first {n_cpu} of the {wl.P} trajectories")
+        cpu = {"value": n_cpu / dt, "unit": "trajectories/s", "cores": nth, "kind": "oracle",
+               "sample": f"{what}, fp64 oracle, {nth} threads, {dt:.1f} s"}
         log(args, f"[bench] oracle: {cpu}")
     roof = None
     if ops_per_traj is not None:
@@ -215,7 +234,8 @@ def main():
                 "traffic_unit": "bytes per launch", "traffic_source": rec[1] if rec else None,
                 "algorithmic_bytes": wl.P * (net.M * 8 + net.N * 4 + net.N * 4 + net.M * 4
                                              + net.M * 8 + lx.STATS_WORDS * 8),
-                "ops_per_trajectory": ops_per_traj, "kernel": "lx_sim_" + hr["schedule"],
+                "ops_per_trajectory": ops_per_traj,
+                "kernel": ("lx_sim_large" if net.N > 16 or net.M > 32 else "lx_sim_" + hr["schedule"]),
                 "kernel_id": hr["kernel_id"]}
     dtype = "f32+f64" if hr["precision"] == "mixed" else "f64"
     line = {
