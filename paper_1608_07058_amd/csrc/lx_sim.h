@@ -397,33 +397,36 @@ struct Lane {
       absorb(prm);
       return;
     }
+    // Selection without branches: the partial sums before the first one
+    // above u2 a0 are those of the ascending search (sums after it are never
+    // compared), and the last reaction with a_j > 0 is used only when no sum
+    // exceeds it, i.e. after every term.
     const R thr_ = u2 * a0;
     R cum = (R)0;
     int jf = -1, jlast = -1;
     bool found = false;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      if (!found) {
-        if (a[j] > (R)0) jlast = j;
-        cum = cum + a[j];
-        if (cum > thr_) {
-          jf = j;
-          found = true;
-        }
-      }
+      jlast = a[j] > (R)0 ? j : jlast;
+      cum = cum + a[j];
+      const bool hit = !found && cum > thr_;
+      jf = hit ? j : jf;
+      found = found || hit;
     }
-    if (!found) jf = jlast;
+    jf = found ? jf : jlast;
 #pragma unroll
     for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * tau_s;
+    // x += nu_jf, r_jf += 1 as selected increments
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      if (j == jf) {
+    for (int i = 0; i < N; ++i) {
+      int d = 0;
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-          if (NET::NU[j][i] != 0) x[i] = x[i] + NET::NU[j][i];
-        r[j] = r[j] + 1;
-      }
+      for (int j = 0; j < M; ++j)
+        if (NET::NU[j][i] != 0) d = (j == jf) ? NET::NU[j][i] : d;
+      x[i] = x[i] + d;
     }
+#pragma unroll
+    for (int j = 0; j < M; ++j) r[j] = r[j] + (j == jf ? 1 : 0);
     t = t + tau_s;
     gvalid = false;
   }

@@ -100,6 +100,26 @@ def test_stiff_padded_elementwise(lxm, orc, precision, mode):
         assert got["stats"]["newton_iters"].sum() > 0
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_random_network_full_ensemble_sampled(lxm, orc, precision):
+    # The random network's full ensemble (65536 trajectories) in the launch
+    # configuration bench.py times for it (batched, default knobs), to
+    # t_end 0.1 (~2100 leaps per trajectory); 48 sampled trajectories, spread
+    # over the grid, are recomputed by the oracle and must agree exactly.
+    wl = W.random_network_workload()
+    net = wl.nets[0]
+    theta, x0 = wl.theta[0], wl.x0[0]
+    got = _gpu(lxm, net, theta, x0, 0.1, "adaptive", precision=precision, schedule="batched")
+    assert np.all(got["stats"]["status"] == 0)
+    idx = np.unique(np.concatenate([np.arange(0, wl.P, wl.P // 40), [1, 255, 256, wl.P - 1]]))
+    for p in idx:
+        ref = orc.simulate(net.m, net.p, theta[p:p + 1], x0[p:p + 1], 0.1, mode="adaptive",
+                           precision=precision, pid_base=int(p), nthreads=1)
+        sub = {"x": got["x"][p:p + 1], "r": got["r"][p:p + 1], "G": got["G"][p:p + 1],
+               "stats": got["stats"][p:p + 1]}
+        _same(sub, ref, f"random full/{precision}/p={p}")
+
+
 def _states(net, Q, rng):
     scale = np.maximum(net.x0, 50)
     x = rng.integers(0, 3 * scale + 1, size=(Q, net.N))
