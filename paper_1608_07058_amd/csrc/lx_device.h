@@ -79,10 +79,11 @@ __device__ __forceinline__ double uniform_f64(u32 hi, u32 lo) {
 //        log(1 + f) = f - f^2/2 + s (f^2/2 + R(s^2)) with R the tail of the
 //        atanh series, plus e ln2 in two parts.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double exp_f64(double x) {
-  if (x != x) return x;
-  if (x > 709.782712893384) return LX_INF_F64;
-  if (x < -745.2) return 0.0;
+// Special arguments are answered by a final select (the main path runs on a
+// harmless argument), so the functions have no divergent branches.
+__device__ __forceinline__ double exp_f64(double x0) {
+  const bool nan = x0 != x0, big = x0 > 709.782712893384, tiny = x0 < -745.2;
+  const double x = (nan || big || tiny) ? 0.0 : x0;
   const double kd = __builtin_floor(x * 0x1.71547652b82fep0 + 0.5);
   const double hi = x - kd * 0x1.62e42feep-1;
   const double r = hi - kd * 0x1.a39ef35793c76p-33;
@@ -100,18 +101,18 @@ __device__ __forceinline__ double exp_f64(double x) {
   p = __builtin_fma(p, r, 0.5);
   p = __builtin_fma(p, r, 1.0);
   p = __builtin_fma(p, r, 1.0);
-  return __builtin_amdgcn_ldexp(p, (int)kd);
+  const double y = __builtin_amdgcn_ldexp(p, (int)kd);
+  return nan ? x0 : (big ? LX_INF_F64 : (tiny ? 0.0 : y));
 }
 
-__device__ __forceinline__ double log_f64(double x) {
-  if (!(x > 0.0)) return x == 0.0 ? -LX_INF_F64 : __builtin_nan("");
-  if (x == LX_INF_F64) return x;
+__device__ __forceinline__ double log_f64(double x0) {
+  const bool normal = x0 > 0.0 && x0 != LX_INF_F64;
+  const double x = normal ? x0 : 1.0;
   double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
   int e = __builtin_amdgcn_frexp_exp(x);
-  if (m < 0x1.6a09e667f3bcdp-1) {
-    m = m + m;
-    e = e - 1;
-  }
+  const bool lo = m < 0x1.6a09e667f3bcdp-1;
+  m = lo ? m + m : m;
+  e = lo ? e - 1 : e;
   const double f = m - 1.0;
   const double hfsq = (0.5 * f) * f;
   const double s = f / (2.0 + f);
@@ -128,13 +129,13 @@ __device__ __forceinline__ double log_f64(double x) {
   q = __builtin_fma(q, z, 2.0 / 3.0);
   const double R = z * q;
   const double ed = (double)e;
-  return ed * 0x1.62e42feep-1 - ((hfsq - (s * (hfsq + R) + ed * 0x1.a39ef35793c76p-33)) - f);
+  const double y = ed * 0x1.62e42feep-1 - ((hfsq - (s * (hfsq + R) + ed * 0x1.a39ef35793c76p-33)) - f);
+  return normal ? y : (x0 == 0.0 ? -LX_INF_F64 : (x0 == LX_INF_F64 ? x0 : __builtin_nan("")));
 }
 
-__device__ __forceinline__ float exp_f32(float x) {
-  if (x != x) return x;
-  if (x > 88.72283f) return LX_INF_F32;
-  if (x < -103.9721f) return 0.0f;
+__device__ __forceinline__ float exp_f32(float x0) {
+  const bool nan = x0 != x0, big = x0 > 88.72283f, tiny = x0 < -103.9721f;
+  const float x = (nan || big || tiny) ? 0.0f : x0;
   const float kf = __builtin_floorf(x * 0x1.715476p0f + 0.5f);
   const float hi = x - kf * 0x1.62e4p-1f;
   const float r = hi - kf * 0x1.7f7d1cp-20f;
@@ -146,18 +147,18 @@ __device__ __forceinline__ float exp_f32(float x) {
   p = __builtin_fmaf(p, r, 0.5f);
   p = __builtin_fmaf(p, r, 1.0f);
   p = __builtin_fmaf(p, r, 1.0f);
-  return __builtin_amdgcn_ldexpf(p, (int)kf);
+  const float y = __builtin_amdgcn_ldexpf(p, (int)kf);
+  return nan ? x0 : (big ? LX_INF_F32 : (tiny ? 0.0f : y));
 }
 
-__device__ __forceinline__ float log_f32(float x) {
-  if (!(x > 0.0f)) return x == 0.0f ? -LX_INF_F32 : __builtin_nanf("");
-  if (x == LX_INF_F32) return x;
+__device__ __forceinline__ float log_f32(float x0) {
+  const bool normal = x0 > 0.0f && x0 != LX_INF_F32;
+  const float x = normal ? x0 : 1.0f;
   float m = __builtin_amdgcn_frexp_mantf(x);
   int e = __builtin_amdgcn_frexp_expf(x);
-  if (m < 0x1.6a09e6p-1f) {
-    m = m + m;
-    e = e - 1;
-  }
+  const bool lo = m < 0x1.6a09e6p-1f;
+  m = lo ? m + m : m;
+  e = lo ? e - 1 : e;
   const float f = m - 1.0f;
   const float hfsq = (0.5f * f) * f;
   const float s = f / (2.0f + f);
@@ -169,7 +170,8 @@ __device__ __forceinline__ float log_f32(float x) {
   q = __builtin_fmaf(q, z, 2.0f / 3.0f);
   const float R = z * q;
   const float ef = (float)e;
-  return ef * 0x1.62e4p-1f - ((hfsq - (s * (hfsq + R) + ef * 0x1.7f7d1cp-20f)) - f);
+  const float y = ef * 0x1.62e4p-1f - ((hfsq - (s * (hfsq + R) + ef * 0x1.7f7d1cp-20f)) - f);
+  return normal ? y : (x0 == 0.0f ? -LX_INF_F32 : (x0 == LX_INF_F32 ? x0 : __builtin_nanf("")));
 }
 
 // log(k!) for integer-valued k >= 0: exact product for k <= 17, Stirling's

@@ -302,8 +302,9 @@ struct Lane {
       R num = eps * (R)x[i];
       if (NET::PHI[i] != 1) num = num / phi(i);
       const R bound = num < (R)1 ? (R)1 : num;
-      const R t1 = (mu != (R)0) ? bound / P::fabs_(mu) : P::inf();
-      const R t2 = (s2 != (R)0) ? (bound * bound) / s2 : P::inf();
+      // bound >= 1, so a zero sum gives +inf by IEEE division (s2 >= +0)
+      const R t1 = bound / P::fabs_(mu);
+      const R t2 = (bound * bound) / s2;
       const R ti = t2 < t1 ? t2 : t1;
       tau = ti < tau ? ti : tau;
     }
@@ -591,22 +592,21 @@ struct Lane {
       tau_r = tau_p;
     } else {
       tau_r = tau_pp;
+      // branch-free search over the critical set, as in the SSA selection
       const R thr_ = uc2 * a0c;
       R cum = (R)0;
       int jlast = -1;
       bool found = false;
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        if (!found && ((crit >> j) & 1u)) {
-          jlast = j;
-          cum = cum + a[j];
-          if (cum > thr_) {
-            jc = j;
-            found = true;
-          }
-        }
+        const bool cj = ((crit >> j) & 1u) != 0u;
+        jlast = cj ? j : jlast;
+        cum = cj ? cum + a[j] : cum;
+        const bool hit = cj && !found && cum > thr_;
+        jc = hit ? j : jc;
+        found = found || hit;
       }
-      if (!found) jc = jlast;
+      jc = found ? jc : jlast;
     }
     double tau = (double)tau_r;
     const double rem = prm.t_end - t;
@@ -630,7 +630,7 @@ struct Lane {
             kj = poisson_sample_call<P>(a[j] * tau_rr, lam_thr, LXP(prm, kcap), key, pid, ea, (u32)j);
           else
             kj = poisson_sample<P>(a[j] * tau_rr, lam_thr, LXP(prm, kcap), key, pid, ea, (u32)j);
-          overflow = overflow || kj < 0;
+          overflow = overflow | (kj < 0);
           k[j] = kj;
         }
       }
@@ -662,7 +662,7 @@ struct Lane {
           if (g * TPL + q < M) {
             const long long v = group_read<TPL>(kj, q);
             k[g * TPL + q] = v;
-            overflow = overflow || v < 0;
+            overflow = overflow | (v < 0);
           }
         }
       }
@@ -685,7 +685,7 @@ struct Lane {
         for (int j = 0; j < M; ++j)
           if (NET::NU[j][i] != 0) v = v + (long long)NET::NU[j][i] * k[j];
         xn[i] = v;
-        ok = ok && v >= 0;
+        ok = ok & (v >= 0);
       }
     }
     if (!ok) {
@@ -695,9 +695,9 @@ struct Lane {
     }
     bool big = false;
 #pragma unroll
-    for (int i = 0; i < N; ++i) big = big || xn[i] > 2147483647LL;
+    for (int i = 0; i < N; ++i) big = big | (xn[i] > 2147483647LL);
 #pragma unroll
-    for (int j = 0; j < M; ++j) big = big || (long long)r[j] + k[j] > 2147483647LL;
+    for (int j = 0; j < M; ++j) big = big | ((long long)r[j] + k[j] > 2147483647LL);
     if (big) {
       status = LANE_COUNT_OVERFLOW;
       return;

@@ -186,8 +186,9 @@ struct LaneL {
       R num = eps * (R)x[i];
       if (NET::PHI[i] != 1) num = num / phi(i);
       const R bound = num < (R)1 ? (R)1 : num;
-      const R t1 = (mu != (R)0) ? bound / P::fabs_(mu) : P::inf();
-      const R t2 = (s2 != (R)0) ? (bound * bound) / s2 : P::inf();
+      // bound >= 1, so a zero sum gives +inf by IEEE division (s2 >= +0)
+      const R t1 = bound / P::fabs_(mu);
+      const R t2 = (bound * bound) / s2;
       const R ti = t2 < t1 ? t2 : t1;
       tau = ti < tau ? ti : tau;
     }

@@ -61,6 +61,23 @@ def test_math_bit_exact(lxm, orc):
     assert np.array_equal(lxm.test_math("lfact", k), orc.lfact(k))
 
 
+def test_math_special_arguments(lxm, orc):
+    # overflow/underflow limits, zeros, negatives, infinities, NaN, subnormals
+    inf, nan = np.inf, np.nan
+    x = np.array([nan, inf, -inf, 0.0, -0.0, 709.78, 709.7827128933841, 709.79, 710.0, -745.1,
+                  -745.2, -745.3, -746.0, 1e-300, -1e-300])
+    assert np.array_equal(lxm.test_math("exp_f64", x), orc.exp_f64(x), equal_nan=True)
+    y = np.array([nan, inf, -inf, 0.0, -0.0, -1.0, -1e-300, 5e-324, 1e-310, 2.0**-1022, 1.0,
+                  np.finfo(np.float64).max])
+    assert np.array_equal(lxm.test_math("log_f64", y), orc.log_f64(y), equal_nan=True)
+    xf = np.array([nan, inf, -inf, 0.0, -0.0, 88.72, 88.72283, 88.73, 89.0, -103.97, -103.9721,
+                   -103.98, -104.0], np.float32)
+    assert np.array_equal(lxm.test_math("exp_f32", xf), orc.exp_f32(xf), equal_nan=True)
+    yf = np.array([nan, inf, -inf, 0.0, -0.0, -1.0, 1e-45, 1e-40, 2.0**-126, 1.0,
+                   np.finfo(np.float32).max], np.float32)
+    assert np.array_equal(lxm.test_math("log_f32", yf), orc.log_f32(yf), equal_nan=True)
+
+
 def test_sqrt_is_correctly_rounded(lxm):
     # PTRS needs sqrt; both sides rely on the IEEE correctly rounded operation.
     rng = np.random.default_rng(14)
