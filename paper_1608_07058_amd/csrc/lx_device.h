@@ -79,11 +79,11 @@ __device__ __forceinline__ double uniform_f64(u32 hi, u32 lo) {
 //        log(1 + f) = f - f^2/2 + s (f^2/2 + R(s^2)) with R the tail of the
 //        atanh series, plus e ln2 in two parts.
 // ---------------------------------------------------------------------------
-// Special arguments are answered by a final select (the main path runs on a
-// harmless argument), so the functions have no divergent branches.
-__device__ __forceinline__ double exp_f64(double x0) {
-  const bool nan = x0 != x0, big = x0 > 709.782712893384, tiny = x0 < -745.2;
-  const double x = (nan || big || tiny) ? 0.0 : x0;
+// Each function is a core for ordinary arguments (exp: within the overflow
+// and underflow limits; log: positive and finite) and a wrapper that answers
+// the special arguments with a final select, without divergent branches.
+// The samplers call the cores: their arguments are ordinary by construction.
+__device__ __forceinline__ double exp_core_f64(double x) {
   const double kd = __builtin_floor(x * 0x1.71547652b82fep0 + 0.5);
   const double hi = x - kd * 0x1.62e42feep-1;
   const double r = hi - kd * 0x1.a39ef35793c76p-33;
@@ -101,13 +101,16 @@ __device__ __forceinline__ double exp_f64(double x0) {
   p = __builtin_fma(p, r, 0.5);
   p = __builtin_fma(p, r, 1.0);
   p = __builtin_fma(p, r, 1.0);
-  const double y = __builtin_amdgcn_ldexp(p, (int)kd);
+  return __builtin_amdgcn_ldexp(p, (int)kd);
+}
+
+__device__ __forceinline__ double exp_f64(double x0) {
+  const bool nan = x0 != x0, big = x0 > 709.782712893384, tiny = x0 < -745.2;
+  const double y = exp_core_f64((nan || big || tiny) ? 0.0 : x0);
   return nan ? x0 : (big ? LX_INF_F64 : (tiny ? 0.0 : y));
 }
 
-__device__ __forceinline__ double log_f64(double x0) {
-  const bool normal = x0 > 0.0 && x0 != LX_INF_F64;
-  const double x = normal ? x0 : 1.0;
+__device__ __forceinline__ double log_core_f64(double x) {
   double m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
   int e = __builtin_amdgcn_frexp_exp(x);
   const bool lo = m < 0x1.6a09e667f3bcdp-1;
@@ -129,13 +132,16 @@ __device__ __forceinline__ double log_f64(double x0) {
   q = __builtin_fma(q, z, 2.0 / 3.0);
   const double R = z * q;
   const double ed = (double)e;
-  const double y = ed * 0x1.62e42feep-1 - ((hfsq - (s * (hfsq + R) + ed * 0x1.a39ef35793c76p-33)) - f);
+  return ed * 0x1.62e42feep-1 - ((hfsq - (s * (hfsq + R) + ed * 0x1.a39ef35793c76p-33)) - f);
+}
+
+__device__ __forceinline__ double log_f64(double x0) {
+  const bool normal = x0 > 0.0 && x0 != LX_INF_F64;
+  const double y = log_core_f64(normal ? x0 : 1.0);
   return normal ? y : (x0 == 0.0 ? -LX_INF_F64 : (x0 == LX_INF_F64 ? x0 : __builtin_nan("")));
 }
 
-__device__ __forceinline__ float exp_f32(float x0) {
-  const bool nan = x0 != x0, big = x0 > 88.72283f, tiny = x0 < -103.9721f;
-  const float x = (nan || big || tiny) ? 0.0f : x0;
+__device__ __forceinline__ float exp_core_f32(float x) {
   const float kf = __builtin_floorf(x * 0x1.715476p0f + 0.5f);
   const float hi = x - kf * 0x1.62e4p-1f;
   const float r = hi - kf * 0x1.7f7d1cp-20f;
@@ -147,13 +153,16 @@ __device__ __forceinline__ float exp_f32(float x0) {
   p = __builtin_fmaf(p, r, 0.5f);
   p = __builtin_fmaf(p, r, 1.0f);
   p = __builtin_fmaf(p, r, 1.0f);
-  const float y = __builtin_amdgcn_ldexpf(p, (int)kf);
+  return __builtin_amdgcn_ldexpf(p, (int)kf);
+}
+
+__device__ __forceinline__ float exp_f32(float x0) {
+  const bool nan = x0 != x0, big = x0 > 88.72283f, tiny = x0 < -103.9721f;
+  const float y = exp_core_f32((nan || big || tiny) ? 0.0f : x0);
   return nan ? x0 : (big ? LX_INF_F32 : (tiny ? 0.0f : y));
 }
 
-__device__ __forceinline__ float log_f32(float x0) {
-  const bool normal = x0 > 0.0f && x0 != LX_INF_F32;
-  const float x = normal ? x0 : 1.0f;
+__device__ __forceinline__ float log_core_f32(float x) {
   float m = __builtin_amdgcn_frexp_mantf(x);
   int e = __builtin_amdgcn_frexp_expf(x);
   const bool lo = m < 0x1.6a09e6p-1f;
@@ -170,7 +179,12 @@ __device__ __forceinline__ float log_f32(float x0) {
   q = __builtin_fmaf(q, z, 2.0f / 3.0f);
   const float R = z * q;
   const float ef = (float)e;
-  const float y = ef * 0x1.62e4p-1f - ((hfsq - (s * (hfsq + R) + ef * 0x1.7f7d1cp-20f)) - f);
+  return ef * 0x1.62e4p-1f - ((hfsq - (s * (hfsq + R) + ef * 0x1.7f7d1cp-20f)) - f);
+}
+
+__device__ __forceinline__ float log_f32(float x0) {
+  const bool normal = x0 > 0.0f && x0 != LX_INF_F32;
+  const float y = log_core_f32(normal ? x0 : 1.0f);
   return normal ? y : (x0 == 0.0f ? -LX_INF_F32 : (x0 == LX_INF_F32 ? x0 : __builtin_nanf("")));
 }
 
@@ -197,8 +211,9 @@ __device__ __noinline__ double lfact_f64(double k) {
 struct F64 {
   typedef double R;
   static constexpr bool mixed = false;
-  __device__ static __forceinline__ R ulog(R v) { return log_f64(v); }
-  __device__ static __forceinline__ R uexp(R v) { return exp_f64(v); }
+  // samplers' logs and exps: arguments positive and finite, resp. in [-30, 0)
+  __device__ static __forceinline__ R ulog(R v) { return log_core_f64(v); }
+  __device__ static __forceinline__ R uexp(R v) { return exp_core_f64(v); }
   __device__ static __forceinline__ R sqrt_(R v) { return __builtin_sqrt(v); }
   __device__ static __forceinline__ R floor_(R v) { return __builtin_floor(v); }
   __device__ static __forceinline__ R fabs_(R v) { return __builtin_fabs(v); }
@@ -219,8 +234,8 @@ struct F64 {
 struct Mixed {
   typedef float R;
   static constexpr bool mixed = true;
-  __device__ static __forceinline__ R ulog(R v) { return log_f32(v); }
-  __device__ static __forceinline__ R uexp(R v) { return exp_f32(v); }
+  __device__ static __forceinline__ R ulog(R v) { return log_core_f32(v); }
+  __device__ static __forceinline__ R uexp(R v) { return exp_core_f32(v); }
   __device__ static __forceinline__ R sqrt_(R v) { return __builtin_sqrtf(v); }
   __device__ static __forceinline__ R floor_(R v) { return __builtin_floorf(v); }
   __device__ static __forceinline__ R fabs_(R v) { return __builtin_fabsf(v); }

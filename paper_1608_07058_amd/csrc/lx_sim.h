@@ -101,7 +101,7 @@ struct Lane {
   long long n_nit;
 
   __device__ __forceinline__ bool active(const SimParams& prm) const {
-    return status == LANE_OK && t < prm.t_end;
+    return (status == LANE_OK) & (t < prm.t_end);  // no short circuit: one condition
   }
 
   __device__ __forceinline__ void load(long long p, const double* __restrict__ theta,
@@ -388,16 +388,23 @@ struct Lane {
   }
 
   // The SSA step given its draws: E = -log(u1) of the step's first uniform and
-  // the second uniform u2.
-  __device__ __forceinline__ void ssa_apply(const SimParams& prm, R E, R u2) {
-    e = e + 1;
-    n_ssa += 1;
-    const double tau_s = (double)(E / a0);
+  // the second uniform u2.  With `zero` (a0 = 0) it is the absorption instead
+  // (G_j += g_j (t_end - t), no step counted), with `budget` nothing happens
+  // but the lane's status; a step whose waiting time reaches t_end counts and
+  // absorbs.  Every outcome is selected, without divergent branches; each
+  // quantity is computed by the operations of its own branch.
+  __device__ __forceinline__ void ssa_apply(const SimParams& prm, R E, R u2, bool zero = false,
+                                            bool budget = false) {
+    const bool stepping = !zero && !budget;
+    e = e + (stepping ? 1u : 0u);
+    n_ssa += stepping ? 1u : 0u;
+    status = budget ? (int)LANE_STEP_BUDGET : status;
+    const double tau_s = (double)(E / a0);  // +inf when a0 = 0 (E > 0)
     const double rem = prm.t_end - t;
-    if (tau_s >= rem) {
-      absorb(prm);
-      return;
-    }
+    const bool past = tau_s >= rem;
+    const bool absorbing = zero || (stepping && past);
+    const bool fire = stepping && !past;
+    const double dt = absorbing ? rem : tau_s;
     // Selection without branches: the partial sums before the first one
     // above u2 a0 are those of the ascending search (sums after it are never
     // compared), and the last reaction with a_j > 0 is used only when no sum
@@ -415,9 +422,14 @@ struct Lane {
       found = found || hit;
     }
     jf = found ? jf : jlast;
+    const bool moves = absorbing || fire;
 #pragma unroll
-    for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * tau_s;
-    // x += nu_jf, r_jf += 1 as selected increments
+    for (int j = 0; j < M; ++j) {
+      const double Gn = G[j] + g[j] * dt;
+      G[j] = moves ? Gn : G[j];
+    }
+    // x += nu_jf, r_jf += 1 as selected increments (a firing only)
+    jf = fire ? jf : -1;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       int d = 0;
@@ -428,8 +440,8 @@ struct Lane {
     }
 #pragma unroll
     for (int j = 0; j < M; ++j) r[j] = r[j] + (j == jf ? 1 : 0);
-    t = t + tau_s;
-    gvalid = false;
+    t = absorbing ? prm.t_end : (fire ? t + tau_s : t);
+    gvalid = fire ? false : gvalid;
   }
 
   // Dense LU with partial pivoting (first maximal pivot), in registers.
@@ -783,7 +795,7 @@ struct Lane {
     } else {
       const u32 sub = threadIdx.x & (TPL - 1);
       int done = 0;
-      while (done < kmax && active(prm) && in_ssa(prm)) {
+      while ((done < kmax) & active(prm) & in_ssa(prm)) {
         const Words4 w = draw_block(key, pid, e + sub, SITE_SSA, 0);
         R u1, u2;
         P::uniforms(w, &u1, &u2);
@@ -792,17 +804,14 @@ struct Lane {
         for (int s = 0; s < TPL; ++s) {
           const R Es = group_read<TPL>(E, s);
           const R u2s = group_read<TPL>(u2, s);
-          if (done < kmax && active(prm) && in_ssa(prm)) {
+          if ((done < kmax) & active(prm) & in_ssa(prm)) {
             propensities();
-            if (a0 == (R)0) {
-              absorb(prm);
-            } else if ((long long)e >= LXP(prm, max_steps)) {
-              status = LANE_STEP_BUDGET;
-            } else {
-              ssa_apply(prm, Es, u2s);
-              if (ssa_left > 0) ssa_left -= 1;
-              plan = false;
-            }
+            const bool zero = a0 == (R)0;
+            const bool budget = !zero && (long long)e >= LXP(prm, max_steps);
+            ssa_apply(prm, Es, u2s, zero, budget);
+            const bool stepped = !zero && !budget;
+            ssa_left = (stepped && ssa_left > 0) ? ssa_left - 1 : ssa_left;
+            plan = stepped ? false : plan;
             ++done;
           }
         }
