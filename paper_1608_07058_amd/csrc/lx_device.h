@@ -354,21 +354,37 @@ __device__ __forceinline__ bool ptrs_candidate(const PtrsParams<P>& c, const Wor
   const R u = u0 - (R)0.5;
   const R us = (R)0.5 - P::fabs_(u);
   const R kf = P::floor_((((R)2 * c.a) / us + c.b) * u + c.lam + (R)0.43);
-  if (kf < (R)0 || (double)kf > 1073741824.0) return false;
-  if (us >= (R)0.07 && v <= c.vr) {
+  if constexpr (P::mixed) {
+    // binary32: all outcomes of the transformed-rejection test evaluated
+    // without branches (a wave nearly always holds a lane that needs the
+    // density test): out of range, quick acceptance, quick rejection,
+    // density test.  A candidate out of range takes the test at k = 0,
+    // harmlessly; the accepted set is the one of the sequential test.  In
+    // binary64 the density test costs more than the branches it saves.
+    const bool range = (kf >= (R)0) & ((double)kf <= 1073741824.0);
+    const bool quick = (us >= (R)0.07) & (v <= c.vr);
+    const bool qrej = (us < (R)0.013) & (v > us);
+    const R ks = range ? kf : (R)0;
+    const R hat = c.a / (us * us) + c.b;
+    R fac, rhs;
+    ptrs_log_density<P>(ks, c.lam, &fac, &rhs);
+    const R lhs = P::ulog(((v * c.inv_alpha) * fac) / hat);
+    *k = (long long)ks;
+    return range & (quick | (!qrej & (lhs <= rhs)));
+  } else {
+    if (kf < (R)0 || (double)kf > 1073741824.0) return false;
+    if (us >= (R)0.07 && v <= c.vr) {
+      *k = (long long)kf;
+      return true;
+    }
+    if (us < (R)0.013 && v > us) return false;
+    const R hat = c.a / (us * us) + c.b;
+    R fac, rhs;
+    ptrs_log_density<P>(kf, c.lam, &fac, &rhs);
+    const R lhs = P::ulog(((v * c.inv_alpha) * fac) / hat);
     *k = (long long)kf;
-    return true;
+    return lhs <= rhs;
   }
-  if (us < (R)0.013 && v > us) return false;
-  const R hat = c.a / (us * us) + c.b;
-  R fac, rhs;
-  ptrs_log_density<P>(kf, c.lam, &fac, &rhs);
-  const R lhs = P::ulog(((v * c.inv_alpha) * fac) / hat);
-  if (lhs <= rhs) {
-    *k = (long long)kf;
-    return true;
-  }
-  return false;
 }
 
 // Trials a PTRS draw makes before giving up (then floor(lam); probability
