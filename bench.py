@@ -37,6 +37,8 @@ WORKLOADS = {
     "dimer": "dimer_workload",
     "birth_death": "birth_death_workload",
     "random48x128": "random_network_workload",
+    "mixed_set": "mixed_set_workload",        # three networks in one launch (lx_simulate_set)
+    "telegraph_pf": "telegraph_workload",     # the particle-filter interval loop (lx_pf_*)
 }
 FORMS = {
     "plain_fp64": {"precision": "fp64", "schedule": "plain"},
@@ -62,6 +64,8 @@ def parse():
                     help="dimer (the headline, default) or a secondary single-network workload")
     ap.add_argument("--t-end", type=float, default=0.0,
                     help="override the workload's t_end (secondary workloads only)")
+    ap.add_argument("--options", default="",
+                    help="JSON object of lx options applied to every form (knob exploration)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="trajectories the oracle baseline runs (default: all for the dimer, "
                          "1024 otherwise)")
@@ -128,6 +132,8 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
         opts.update(autotune.lookup(net.m, net.p, wl.P, opts["precision"], wl.mode))
     if args.block_size:
         opts["block_size"] = args.block_size
+    if args.options:
+        opts.update(json.loads(args.options))
     stream = torch.cuda.current_stream()
 
     def launch():
@@ -164,6 +170,161 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
     }
 
 
+def timed(args, torch, launch, stream):
+    """W untimed launches, then K launches bracketed by HIP events on `stream`;
+    returns (mean ms per launch, wall seconds)."""
+    for _ in range(args.warmup):
+        launch()
+    torch.cuda.synchronize()
+    per = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        launch()
+        b.record(stream)
+        b.synchronize()
+        per.append(a.elapsed_time(b))
+    return sum(per) / len(per), time.perf_counter() - t0
+
+
+def line(args, metric_unit, value, ms, dtype, config, extra):
+    out = {"metric": METRIC, "value": value, "unit": metric_unit, "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_set(args, torch, lx, W):
+    """Three networks in one launch (lx_simulate_set): particle p runs network
+    p mod 3 (its RNG particle id), batched schedule."""
+    wl = W.mixed_set_workload()
+    hs = [lx.Network(n.m, n.p) for n in wl.nets]
+    th = [torch.as_tensor(t, device="cuda") for t in wl.theta]
+    xx = [torch.as_tensor(x, device="cuda") for x in wl.x0]
+    outs = [None] * len(hs)
+    results = {}
+    for form in [f for f in args.forms.split(",") if f.startswith("batched")]:
+        opts = dict(FORMS[form])
+        opts.pop("schedule")
+        if args.options:
+            opts.update(json.loads(args.options))
+        stream = torch.cuda.current_stream()
+
+        def launch():
+            items = [{"net": h, "theta": t, "x0": x, "pid_base": k, "pid_stride": len(hs),
+                      "out": outs[k]} for k, (h, t, x) in enumerate(zip(hs, th, xx))]
+            res = lx.simulate_set(items, wl.t_end, wl.eps, wl.mode, stream=stream, **opts)
+            for k in range(len(hs)):
+                outs[k] = res[k]
+
+        ms, wall = timed(args, torch, launch, stream)
+        r_total = sum(int(o["r"].sum(dtype=torch.int64).item()) for o in outs)
+        ok = all(bool((lx.stats_numpy(o["stats"])["status"] == 0).all()) for o in outs)
+        results[form] = {"ms_per_step": ms, "wall_s": wall, "trajectories_per_s": wl.P / (ms / 1e3),
+                         "events_per_s": r_total / (ms / 1e3), "lane_status_ok": ok,
+                         "precision": opts["precision"], "options": opts}
+        log(args, f"[bench] {form}: {results[form]}")
+    head = args.headline if args.headline in results else sorted(results)[0]
+    hr = results[head]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
+        n_cpu = args.cpu_sample or 8192
+        t0 = time.perf_counter()
+        for k, net in enumerate(wl.nets):
+            oracle.simulate(net.m, net.p, wl.theta[k][:n_cpu], wl.x0[k][:n_cpu], wl.t_end,
+                            mode=wl.mode, nthreads=nth, pid_base=k, pid_stride=len(wl.nets))
+        dt = time.perf_counter() - t0
+        cpu = {"value": len(wl.nets) * n_cpu / dt, "unit": "trajectories/s", "cores": nth,
+               "kind": "oracle", "sample": f"the first {n_cpu} trajectories of each network, "
+                                           f"fp64 oracle, {nth} threads, {dt:.1f} s"}
+    line(args, "trajectories/s", hr["trajectories_per_s"], hr["ms_per_step"],
+         "f32+f64" if hr["precision"] == "mixed" else "f64",
+         {"workload": wl.name, "trajectories": wl.P, "t_end": wl.t_end, "eps": wl.eps,
+          "mode": wl.mode, "form": head},
+         {"events_per_s": hr["events_per_s"], "forms": results, "roofline": None,
+          "cpu_baseline": cpu})
+
+
+def bench_pf(args, torch, lx, W):
+    """The particle-filter interval loop: 2^18 particles of the telegraph model
+    x 50 observation intervals of length 5, captured once into a HIP graph;
+    a step is one replay of all 50 intervals.  Observations: a seeded random
+    walk of the protein level (synthetic)."""
+    import numpy as np
+    wl = W.telegraph_workload()
+    net = wl.nets[0]
+    K, dt, obs, sd = 50, 5.0, 3, 10.0
+    rng = np.random.default_rng(9)
+    y = np.clip(100.0 + np.cumsum(rng.normal(0.0, 15.0, K)), 0.0, None)
+    h = lx.Network(net.m, net.p)
+    th0 = torch.as_tensor(wl.theta[0], device="cuda")
+    x00 = torch.as_tensor(wl.x0[0], device="cuda")
+    results = {}
+    for form in [f for f in args.forms.split(",") if f.startswith("batched")]:
+        opts = dict(FORMS[form])
+        if args.options:
+            opts.update(json.loads(args.options))
+        th = th0.clone()
+        xx = x00.clone()
+        pf = lx.ParticleFilter(h, th, xx, torch.as_tensor(y, device="cuda"),
+                               torch.full((net.M,), 2.0, dtype=torch.float64, device="cuda"),
+                               torch.as_tensor(2.0 / net.theta, device="cuda"), dt, obs, sd,
+                               **opts)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            pf.capture(s)
+
+        def reset():
+            pf.theta.copy_(th0)
+            pf.x.copy_(x00)
+            pf.r.zero_()
+            pf.G.zero_()
+            torch.cuda.synchronize()
+
+        per = []
+        for k in range(args.warmup + args.steps):
+            reset()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            pf.replay(s)
+            b.record(s)
+            b.synchronize()
+            if k >= args.warmup:
+                per.append(a.elapsed_time(b))
+        ms = sum(per) / len(per)
+        ll = pf.loglik.cpu().numpy()
+        results[form] = {"ms_per_step": ms, "particle_intervals_per_s": wl.P * K / (ms / 1e3),
+                         "loglik_finite": bool(np.isfinite(ll).all()),
+                         "precision": opts["precision"], "options": opts}
+        pf.release()
+        log(args, f"[bench] {form}: {results[form]}")
+    head = args.headline if args.headline in results else sorted(results)[0]
+    hr = results[head]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
+        n_cpu = args.cpu_sample or 65536
+        t0 = time.perf_counter()
+        oracle.pf_run(net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu], K, dt, obs, sd, y,
+                      np.full(net.M, 2.0), 2.0 / net.theta, nthreads=nth)
+        dtc = time.perf_counter() - t0
+        cpu = {"value": n_cpu * K / dtc, "unit": "particle-intervals/s", "cores": nth,
+               "kind": "oracle", "sample": f"{n_cpu} particles x {K} intervals, fp64 oracle "
+                                           f"filter, {dtc:.1f} s"}
+    line(args, "particle-intervals/s", hr["particle_intervals_per_s"], hr["ms_per_step"],
+         "f32+f64" if hr["precision"] == "mixed" else "f64",
+         {"workload": wl.name, "particles": wl.P, "intervals": K, "dt": dt, "form": head},
+         {"forms": results, "roofline": None, "cpu_baseline": cpu})
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -178,6 +339,10 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.workload == "mixed_set":
+        return bench_set(args, torch, lx, W)
+    if args.workload == "telegraph_pf":
+        return bench_pf(args, torch, lx, W)
     wl = getattr(W, WORKLOADS[args.workload])()
     if args.t_end > 0.0:
         if args.workload == "dimer":
