@@ -78,6 +78,9 @@ def lib():
         L.orc_simulate.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int64, P, P, C.c_double,
                                    C.POINTER(Options), P, P, P, P]
         L.orc_simulate.restype = C.c_int
+        L.orc_simulate_grid.argtypes = [C.c_int32, C.c_int32, P, P, C.c_int64, P, P, C.c_int32,
+                                        P, C.POINTER(Options), P, P, P, P, P]
+        L.orc_simulate_grid.restype = C.c_int
         L.orc_philox.argtypes = [C.c_int64, P, P, P]
         L.orc_uniform_f64.argtypes = [C.c_int64, P, P]
         L.orc_uniform_f32.argtypes = [C.c_int64, P, P]
@@ -159,6 +162,38 @@ def simulate(m, p, theta, x0, t_end, *, r0=None, G0=None, **kw):
     if rc != 0:
         raise ValueError(f"oracle rejected the network or options (code {rc})")
     return {"x": x, "r": r, "G": G, "stats": st}
+
+
+def simulate_grid(m, p, theta, x0, times, *, r0=None, G0=None, **kw):
+    """``simulate`` with observation times: the state at each of ``times``
+    (non-decreasing, from t_start; the last one ends the simulation) as
+    x_grid [P][K][N] int32, -1 where a trajectory did not reach a time in
+    status OK.  Returns the dict of ``simulate`` plus ``x_grid``."""
+    m, p = _net_arrays(m, p)
+    M, N = m.shape
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    times = np.ascontiguousarray(times, dtype=np.float64).reshape(-1)
+    P, K = theta.shape[0], times.shape[0]
+    if theta.shape != (P, M) or x0.shape != (P, N):
+        raise ValueError("theta must be [P][M] and x0 [P][N]")
+    if K < 1:
+        raise ValueError("need at least one observation time")
+    kw.setdefault("nthreads", min(16, os.cpu_count() or 1))
+    o = options(**kw)
+    xg = np.empty((P, K, N), np.int32)
+    x = np.empty((P, N), np.int32)
+    r = np.zeros((P, M), np.int32) if r0 is None else np.array(r0, dtype=np.int32, copy=True)
+    G = np.zeros((P, M), np.float64) if G0 is None else np.array(G0, dtype=np.float64, copy=True)
+    if r0 is not None or G0 is not None:
+        o.accumulate = 1
+    st = np.zeros(P, STATS_DTYPE)
+    rc = lib().orc_simulate_grid(N, M, _ptr(m), _ptr(p), P, _ptr(theta), _ptr(x0), K,
+                                 _ptr(times), C.byref(o), _ptr(xg), _ptr(x), _ptr(r), _ptr(G),
+                                 _ptr(st))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the network, options or times (code {rc})")
+    return {"x_grid": xg, "x": x, "r": r, "G": G, "stats": st}
 
 
 def philox(ctr, key):

@@ -868,8 +868,19 @@ struct Traj {
     return true;
   }
 
+  // Observation times (time-grid output, reading of the paper's accuracy
+  // measurement at fixed time points): with K > 0 the trajectory stops at
+  // each times[k] exactly as it stops at t_end (leaps clipped without a
+  // critical firing, an SSA step that would pass the time integrates g to it
+  // and does not fire, an absorbing state integrates g to it), its state is
+  // recorded in xg[k][N], and it goes on from there with the same random
+  // stream (attempt counter) and fresh step decisions.  A time below the
+  // current time, or not finite, ends the trajectory with BAD_INPUT; rows of
+  // times the trajectory does not reach in status OK hold -1.  The last time
+  // is the end of the simulation (t_end is not used).
   void run(uint32_t pid, const double* th, const int32_t* x0, int32_t* xo, int32_t* ro,
-           double* Go, orc_stats* so) {
+           double* Go, orc_stats* so, int K = 0, const double* times = nullptr,
+           int32_t* xg = nullptr) {
     rng.key[0] = (uint32_t)o.seed;
     rng.key[1] = (uint32_t)(o.seed >> 32) + o.rng_stream;
     rng.pid = pid;
@@ -894,144 +905,155 @@ struct Traj {
     const R lam_thr = (R)o.lambda_thr;
     const int kcap = 20 + 4 * (int)std::ceil(o.lambda_thr);
 
-    while (status == ST_OK && t < t_end) {
-      propensities();
-      if (a0 == (R)0) {  // absorbing state (reading): integrate g to t_end
-        double rem = t_end - t;
-        for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * rem;
-        t = t_end;
-        break;
+    const int nseg = K > 0 ? K : 1;
+    for (int kt = 0; kt < nseg; ++kt) {
+      if (K > 0 && status == ST_OK) {
+        if (!(times[kt] >= t) || times[kt] == std::numeric_limits<double>::infinity())
+          status = ST_BAD_INPUT;
+        else
+          t_end = times[kt];
       }
-      if (o.mode == MODE_SSA) {
-        if ((int64_t)e >= o.max_steps) { status = ST_STEP_BUDGET; break; }
-        ssa_step();
-        continue;
-      }
-      critical_set();
-      R tau_ex = tau_select(ncr);
-      bool implicit = false;
-      R tau_p = tau_ex;
-      if (o.mode == MODE_ADAPTIVE && net.npairs > 0 && equilibrium_set()) {
-        std::vector<int> use(M);
-        for (int j = 0; j < M; ++j) use[j] = ncr[j] && !eq[j];
-        R tau_im = tau_select(use);
-        if (tau_im > n_stiff * tau_ex) {  // "much greater" (Implementation section)
-          implicit = true;
-          tau_p = tau_im;
-        }
-      }
-      // Leap attempts with the same propensities; tau' halves on rejection.
-      for (;;) {
-        count_ops(4);
-        if (tau_p < k_ssa / a0 || a0c >= a0 / k_crit) {
-          // SSA burst: Cao 2006 fallback when the leap is a few SSA steps,
-          // and the matLeap switch when critical reactions are fast.
-          int n = implicit ? o.n_ssa_im : o.n_ssa_ex;
-          for (int s = 0; s < n && t < t_end; ++s) {
-            if ((int64_t)e >= o.max_steps) { status = ST_STEP_BUDGET; break; }
-            if (s > 0) {
-              propensities();
-              if (a0 == (R)0) {
-                double rem = t_end - t;
-                for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * rem;
-                t = t_end;
-                break;
-              }
-            }
-            ssa_step();
-          }
+      while (status == ST_OK && t < t_end) {
+        propensities();
+        if (a0 == (R)0) {  // absorbing state (reading): integrate g to t_end
+          double rem = t_end - t;
+          for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * rem;
+          t = t_end;
           break;
         }
-        if ((int64_t)e >= o.max_steps) { status = ST_STEP_BUDGET; break; }
-        const uint32_t ea = e;
-        e = e + 1;
-        // Critical firing: tau'' ~ Exp(a0c); one critical reaction fires if
-        // it comes before the leap (Cao 2006).
-        R tau_pp = inf;
-        int jc = -1;
-        uint32_t wc[4];
-        R uc1 = 0, uc2 = 0;
-        if (a0c > (R)0) {
-          rng.block(ea, SITE_CRIT, 0, wc);
-          P::two_uniforms(wc, &uc1, &uc2);
-          tau_pp = -P::ulog(uc1) / a0c;
-        }
-        R tau_r;
-        if (tau_p < tau_pp) {
-          tau_r = tau_p;
-        } else {
-          tau_r = tau_pp;
-          R thr = uc2 * a0c, cum = 0;
-          int jlast = -1;
-          for (int j = 0; j < M; ++j) {
-            if (!crit[j]) continue;
-            jlast = j;
-            count_ops(2);
-            cum = cum + a[j];
-            if (cum > thr) { jc = j; break; }
-          }
-          if (jc < 0) jc = jlast;
-        }
-        double tau = (double)tau_r;
-        double rem = t_end - t;
-        bool last = false;
-        if (tau >= rem) {  // clip at t_end; no critical firing (reading)
-          tau = rem;
-          jc = -1;
-          last = true;
-        }
-        R tau_rr = (R)tau;
-        count_ops(6);
-        // Poisson counts of the non-critical reactions, ascending j.
-        bool overflow = false;
-        for (int j = 0; j < M; ++j) {
-          k[j] = 0;
-          if (!ncr[j]) continue;
-          count_ops(1);
-          int64_t kj = poisson_sample<P>(a[j] * tau_rr, lam_thr, kcap, rng, ea, (uint32_t)j);
-          if (kj < 0) overflow = true;
-          k[j] = kj;
-        }
-        if (overflow) { status = ST_LAMBDA_OVERFLOW; break; }
-        bool ok = true;
-        if (implicit) {
-          std::vector<int64_t> Pj(k);
-          ok = implicit_counts(tau, Pj, jc);
-        }
-        if (ok) {
-          if (jc >= 0) k[jc] = 1;
-          uint64_t nnz = 0;
-          for (int j = 0; j < M; ++j) nnz += (uint64_t)net.nu_nnz[j];
-          count_ops(2 * nnz + (uint64_t)N);
-          for (int i = 0; i < N; ++i) {
-            int64_t v = x[i];
-            for (int j = 0; j < M; ++j) v = v + (int64_t)net.nu[j * N + i] * k[j];
-            xnew[i] = v;
-            if (v < 0) ok = false;
-          }
-        }
-        if (!ok) {  // negative population or failed solve: halve tau' (Cao 2006)
-          st.rejections += 1;
-          tau_p = tau_p / (R)2;
+        if (o.mode == MODE_SSA) {
+          if ((int64_t)e >= o.max_steps) { status = ST_STEP_BUDGET; break; }
+          ssa_step();
           continue;
         }
-        bool big = false;
-        for (int i = 0; i < N; ++i) big = big || xnew[i] > 2147483647LL;
-        for (int j = 0; j < M; ++j) big = big || r[j] + k[j] > 2147483647LL;
-        if (big) { status = ST_COUNT_OVERFLOW; break; }
-        // Accept: trapezoid rule for G over the leap, for every reaction.
-        count_ops(net.g_cost + 5 * (uint64_t)M + (uint64_t)N + 2);
-        g_all(xnew, gnew);
-        for (int j = 0; j < M; ++j) {
-          G[j] = G[j] + (tau * (g[j] + gnew[j])) * 0.5;
-          r[j] = r[j] + k[j];
+        critical_set();
+        R tau_ex = tau_select(ncr);
+        bool implicit = false;
+        R tau_p = tau_ex;
+        if (o.mode == MODE_ADAPTIVE && net.npairs > 0 && equilibrium_set()) {
+          std::vector<int> use(M);
+          for (int j = 0; j < M; ++j) use[j] = ncr[j] && !eq[j];
+          R tau_im = tau_select(use);
+          if (tau_im > n_stiff * tau_ex) {  // "much greater" (Implementation section)
+            implicit = true;
+            tau_p = tau_im;
+          }
         }
-        for (int i = 0; i < N; ++i) x[i] = xnew[i];
-        t = last ? t_end : t + tau;
-        if (implicit) st.steps_implicit += 1;
-        else st.steps_explicit += 1;
-        break;
+        // Leap attempts with the same propensities; tau' halves on rejection.
+        for (;;) {
+          count_ops(4);
+          if (tau_p < k_ssa / a0 || a0c >= a0 / k_crit) {
+            // SSA burst: Cao 2006 fallback when the leap is a few SSA steps,
+            // and the matLeap switch when critical reactions are fast.
+            int n = implicit ? o.n_ssa_im : o.n_ssa_ex;
+            for (int s = 0; s < n && t < t_end; ++s) {
+              if ((int64_t)e >= o.max_steps) { status = ST_STEP_BUDGET; break; }
+              if (s > 0) {
+                propensities();
+                if (a0 == (R)0) {
+                  double rem = t_end - t;
+                  for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * rem;
+                  t = t_end;
+                  break;
+                }
+              }
+              ssa_step();
+            }
+            break;
+          }
+          if ((int64_t)e >= o.max_steps) { status = ST_STEP_BUDGET; break; }
+          const uint32_t ea = e;
+          e = e + 1;
+          // Critical firing: tau'' ~ Exp(a0c); one critical reaction fires if
+          // it comes before the leap (Cao 2006).
+          R tau_pp = inf;
+          int jc = -1;
+          uint32_t wc[4];
+          R uc1 = 0, uc2 = 0;
+          if (a0c > (R)0) {
+            rng.block(ea, SITE_CRIT, 0, wc);
+            P::two_uniforms(wc, &uc1, &uc2);
+            tau_pp = -P::ulog(uc1) / a0c;
+          }
+          R tau_r;
+          if (tau_p < tau_pp) {
+            tau_r = tau_p;
+          } else {
+            tau_r = tau_pp;
+            R thr = uc2 * a0c, cum = 0;
+            int jlast = -1;
+            for (int j = 0; j < M; ++j) {
+              if (!crit[j]) continue;
+              jlast = j;
+              count_ops(2);
+              cum = cum + a[j];
+              if (cum > thr) { jc = j; break; }
+            }
+            if (jc < 0) jc = jlast;
+          }
+          double tau = (double)tau_r;
+          double rem = t_end - t;
+          bool last = false;
+          if (tau >= rem) {  // clip at t_end; no critical firing (reading)
+            tau = rem;
+            jc = -1;
+            last = true;
+          }
+          R tau_rr = (R)tau;
+          count_ops(6);
+          // Poisson counts of the non-critical reactions, ascending j.
+          bool overflow = false;
+          for (int j = 0; j < M; ++j) {
+            k[j] = 0;
+            if (!ncr[j]) continue;
+            count_ops(1);
+            int64_t kj = poisson_sample<P>(a[j] * tau_rr, lam_thr, kcap, rng, ea, (uint32_t)j);
+            if (kj < 0) overflow = true;
+            k[j] = kj;
+          }
+          if (overflow) { status = ST_LAMBDA_OVERFLOW; break; }
+          bool ok = true;
+          if (implicit) {
+            std::vector<int64_t> Pj(k);
+            ok = implicit_counts(tau, Pj, jc);
+          }
+          if (ok) {
+            if (jc >= 0) k[jc] = 1;
+            uint64_t nnz = 0;
+            for (int j = 0; j < M; ++j) nnz += (uint64_t)net.nu_nnz[j];
+            count_ops(2 * nnz + (uint64_t)N);
+            for (int i = 0; i < N; ++i) {
+              int64_t v = x[i];
+              for (int j = 0; j < M; ++j) v = v + (int64_t)net.nu[j * N + i] * k[j];
+              xnew[i] = v;
+              if (v < 0) ok = false;
+            }
+          }
+          if (!ok) {  // negative population or failed solve: halve tau' (Cao 2006)
+            st.rejections += 1;
+            tau_p = tau_p / (R)2;
+            continue;
+          }
+          bool big = false;
+          for (int i = 0; i < N; ++i) big = big || xnew[i] > 2147483647LL;
+          for (int j = 0; j < M; ++j) big = big || r[j] + k[j] > 2147483647LL;
+          if (big) { status = ST_COUNT_OVERFLOW; break; }
+          // Accept: trapezoid rule for G over the leap, for every reaction.
+          count_ops(net.g_cost + 5 * (uint64_t)M + (uint64_t)N + 2);
+          g_all(xnew, gnew);
+          for (int j = 0; j < M; ++j) {
+            G[j] = G[j] + (tau * (g[j] + gnew[j])) * 0.5;
+            r[j] = r[j] + k[j];
+          }
+          for (int i = 0; i < N; ++i) x[i] = xnew[i];
+          t = last ? t_end : t + tau;
+          if (implicit) st.steps_implicit += 1;
+          else st.steps_explicit += 1;
+          break;
+        }
       }
+      if (K > 0)
+        for (int i = 0; i < N; ++i) xg[(size_t)kt * N + i] = status == ST_OK ? (int32_t)x[i] : -1;
     }
     for (int i = 0; i < N; ++i) xo[i] = (int32_t)x[i];
     for (int j = 0; j < M; ++j) {
@@ -1089,14 +1111,42 @@ uint64_t scale_u64(uint64_t r, uint64_t S) {
 template <class P>
 void run_range(const Net& net, const orc_options& o, double t_end, int64_t lo, int64_t hi,
                const double* theta, const int32_t* x0, int32_t* xo, int32_t* ro, double* Go,
-               orc_stats* so) {
+               orc_stats* so, int K, const double* times, int32_t* xg) {
   const int N = net.N, M = net.M;
   for (int64_t p = lo; p < hi; ++p) {
     Traj<P> tr(net, o, t_end);
     const uint32_t stride = o.pid_stride ? o.pid_stride : 1;
     tr.run(o.pid_base + (uint32_t)p * stride, theta + p * M, x0 + p * N, xo + p * N, ro + p * M,
-           Go + p * M, so ? so + p : nullptr);
+           Go + p * M, so ? so + p : nullptr, K, times, xg ? xg + (size_t)p * K * N : nullptr);
   }
+}
+
+int simulate_impl(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab, int64_t P,
+                  const double* theta, const int32_t* x0, double t_end, const orc_options* opt,
+                  int32_t* x_out, int32_t* r_out, double* G_out, orc_stats* stats, int K,
+                  const double* times, int32_t* xg) {
+  Net net;
+  if (build_net(N, M, mtab, ptab, &net) != 0) return -1;
+  const orc_options& o = *opt;
+  if (!(o.lambda_thr >= 1.0 && o.lambda_thr <= 30.0) || o.n_c < 0 || o.mode < 0 || o.mode > 2 ||
+      !(t_end >= o.t_start) || !(o.eps > 0.0) || o.precision < 0 || o.precision > 1)
+    return -2;
+  int nth = o.nthreads > 0 ? o.nthreads : (int)std::max(1u, std::thread::hardware_concurrency());
+  nth = (int)std::min<int64_t>(nth, std::max<int64_t>(P, 1));
+  std::vector<std::thread> pool;
+  int64_t chunk = (P + nth - 1) / nth;
+  for (int tix = 0; tix < nth; ++tix) {
+    int64_t lo = tix * chunk, hi = std::min(P, lo + chunk);
+    if (lo >= hi) break;
+    if (o.precision == 0)
+      pool.emplace_back(run_range<PolicyF64>, std::cref(net), std::cref(o), t_end, lo, hi, theta,
+                        x0, x_out, r_out, G_out, stats, K, times, xg);
+    else
+      pool.emplace_back(run_range<PolicyMixed>, std::cref(net), std::cref(o), t_end, lo, hi,
+                        theta, x0, x_out, r_out, G_out, stats, K, times, xg);
+  }
+  for (auto& th : pool) th.join();
+  return 0;
 }
 
 }  // namespace
@@ -1132,28 +1182,20 @@ int orc_stats_size(void) { return (int)sizeof(orc_stats); }
 int orc_simulate(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab, int64_t P,
                  const double* theta, const int32_t* x0, double t_end, const orc_options* opt,
                  int32_t* x_out, int32_t* r_out, double* G_out, orc_stats* stats) {
-  Net net;
-  if (build_net(N, M, mtab, ptab, &net) != 0) return -1;
-  const orc_options& o = *opt;
-  if (!(o.lambda_thr >= 1.0 && o.lambda_thr <= 30.0) || o.n_c < 0 || o.mode < 0 || o.mode > 2 ||
-      !(t_end >= o.t_start) || !(o.eps > 0.0) || o.precision < 0 || o.precision > 1)
-    return -2;
-  int nth = o.nthreads > 0 ? o.nthreads : (int)std::max(1u, std::thread::hardware_concurrency());
-  nth = (int)std::min<int64_t>(nth, std::max<int64_t>(P, 1));
-  std::vector<std::thread> pool;
-  int64_t chunk = (P + nth - 1) / nth;
-  for (int tix = 0; tix < nth; ++tix) {
-    int64_t lo = tix * chunk, hi = std::min(P, lo + chunk);
-    if (lo >= hi) break;
-    if (o.precision == 0)
-      pool.emplace_back(run_range<PolicyF64>, std::cref(net), std::cref(o), t_end, lo, hi, theta,
-                        x0, x_out, r_out, G_out, stats);
-    else
-      pool.emplace_back(run_range<PolicyMixed>, std::cref(net), std::cref(o), t_end, lo, hi,
-                        theta, x0, x_out, r_out, G_out, stats);
-  }
-  for (auto& th : pool) th.join();
-  return 0;
+  return simulate_impl(N, M, mtab, ptab, P, theta, x0, t_end, opt, x_out, r_out, G_out, stats,
+                       0, nullptr, nullptr);
+}
+
+// As orc_simulate with observation times times[0..K) (K >= 1): the state at
+// each time goes to x_grid [P][K][N] (see Traj::run); the simulation ends at
+// times[K-1].  Returns -3 for K < 1.
+int orc_simulate_grid(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab, int64_t P,
+                      const double* theta, const int32_t* x0, int32_t K, const double* times,
+                      const orc_options* opt, int32_t* x_grid, int32_t* x_out, int32_t* r_out,
+                      double* G_out, orc_stats* stats) {
+  if (K < 1 || !times) return -3;
+  return simulate_impl(N, M, mtab, ptab, P, theta, x0, opt->t_start, opt, x_out, r_out, G_out,
+                       stats, K, times, x_grid);
 }
 
 // ---- element-wise hooks on fixed inputs (for pins and bit-exact checks) ----
