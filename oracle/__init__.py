@@ -40,7 +40,7 @@ class Options(C.Structure):
         ("n_c", C.c_int32), ("n_ssa_ex", C.c_int32), ("n_ssa_im", C.c_int32),
         ("newton_maxit", C.c_int32), ("rng_stream", C.c_uint32), ("pid_base", C.c_uint32),
         ("accumulate", C.c_int32), ("mode", C.c_int32), ("precision", C.c_int32),
-        ("nthreads", C.c_int32), ("pid_stride", C.c_uint32), ("pad", C.c_uint32),
+        ("nthreads", C.c_int32), ("pid_stride", C.c_uint32), ("jacobian", C.c_int32),
     ]
 
 

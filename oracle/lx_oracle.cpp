@@ -584,7 +584,8 @@ typedef struct {
   int32_t n_c, n_ssa_ex, n_ssa_im, newton_maxit;
   uint32_t rng_stream, pid_base;
   int32_t accumulate, mode, precision, nthreads;
-  uint32_t pid_stride, pad;  // particle p uses id pid_base + p * pid_stride (0 means 1)
+  uint32_t pid_stride;  // particle p uses id pid_base + p * pid_stride (0 means 1)
+  int32_t jacobian;     // 0: analytic mass-action Jacobian, 1: forward differences
 } orc_options;
 
 typedef struct {
@@ -799,9 +800,27 @@ struct Traj {
     return true;
   }
 
+  // Forward-difference estimate of d a_j / d y_k at y (the numerically
+  // estimated Jacobian the paper names as the alternative to a symbolic one,
+  // Background): the step h_k = 2^-26 max(|y_k|, 1) (square root of the
+  // binary64 epsilon, scaled), taken as the representable difference
+  // (y_k + h_k) - y_k, and a_j re-evaluated with y_k moved by it.
+  double fd_dadk(int j, int kk, std::vector<double>& y, double ayj) {
+    count_ops(8);
+    const double yk = y[kk];
+    const double step = 0x1p-26 * std::max(std::fabs(yk), 1.0);
+    const double yh = yk + step;
+    const double h = yh - yk;
+    y[kk] = yh;
+    const double ayh = theta[j] * g_of(net, j, y.data());
+    y[kk] = yk;
+    return (ayh - ayj) / h;
+  }
+
   // Implicit tau-leap (Rathinam et al. 2003): solve for real y
   //   y = x + sum_{j noncritical} nu_j (tau a_j(y) - tau a_j(x) + P_j) + nu_jc [fired]
-  // by Newton with the analytic Jacobian I - tau sum_j nu_j grad a_j(y)^T.
+  // by Newton with the Jacobian I - tau sum_j nu_j grad a_j(y)^T, its entries
+  // analytic (mass-action derivative) or forward differences (fd_dadk).
   // On success writes k_j = max(0, round(tau a_j(y) - tau a_j(x) + P_j)).
   bool implicit_counts(double tau, const std::vector<int64_t>& Pj, int jc) {
     std::vector<double> c(N), y(N), F(N), J((size_t)N * N), ax(M), ay(M);
@@ -837,7 +856,9 @@ struct Traj {
           double s = 0.0;
           for (int j = 0; j < M; ++j) {
             if (!ncr[j] || net.nu[j * N + i] == 0 || net.m[j * N + kk] == 0) continue;
-            s = s + (double)net.nu[j * N + i] * (theta[j] * dg_of(net, j, kk, y.data()));
+            const double d = o.jacobian ? fd_dadk(j, kk, y, ay[j])
+                                        : theta[j] * dg_of(net, j, kk, y.data());
+            s = s + (double)net.nu[j * N + i] * d;
           }
           J[i * N + kk] = (i == kk ? 1.0 : 0.0) - tau * s;
         }

@@ -127,6 +127,47 @@ def test_implicit_nonlinear_residual_vanishes(orc):
         assert np.all(res["k"][0] >= 0)
 
 
+def test_implicit_fd_jacobian_linear_network(orc):
+    # forward differences of an affine a(y) are exact up to the rounding of
+    # the step: Newton still lands on the direct solution
+    net = W.isomerisation(kf=3.0, kb=1.5)
+    rng = np.random.default_rng(17)
+    nu = (net.p - net.m).T.astype(float)
+    K = np.diag(net.theta) @ net.m.astype(float)
+    for _ in range(20):
+        x = rng.integers(20, 2000, size=2)
+        tau = float(rng.uniform(0.01, 5.0))
+        Pj = rng.integers(0, 500, size=2)
+        res = orc.implicit(net.m, net.p, net.theta, x, tau, Pj, -1, jacobian=1)
+        assert res["ok"][0]
+        y = np.linalg.solve(np.eye(2) - tau * nu @ K, x + nu @ (Pj - tau * (K @ x)))
+        assert np.allclose(res["y"][0], y, rtol=1e-10, atol=1e-8)
+        assert res["iters"][0] <= 3
+
+
+@pytest.mark.parametrize("name", ["dimer", "dimer_stiff", "schlogl"])
+def test_implicit_fd_jacobian_finds_the_analytic_root(orc, name):
+    # Newton with the forward-difference Jacobian converges to the root the
+    # analytic Jacobian finds (same residual, tolerance 1e-10), in at most a
+    # few more iterations; rounded counts agree except at rounding ties
+    net = {"dimer": W.dimer(), "dimer_stiff": W.dimer_stiff(), "schlogl": W.schlogl()}[name]
+    rng = np.random.default_rng(18)
+    Q = 400
+    x = rng.integers(50, 5000, size=(Q, net.N)).astype(np.int32)
+    tau = rng.uniform(1e-4, 0.05, Q)
+    a = orc.tau_select(net.m, net.p, np.tile(net.theta, (Q, 1)), x)["a"]
+    Pj = rng.poisson(np.minimum(a * tau[:, None], 1e6))
+    ana = orc.implicit(net.m, net.p, net.theta, x, tau, Pj, -1)
+    fd = orc.implicit(net.m, net.p, net.theta, x, tau, Pj, -1, jacobian=1)
+    both = ana["ok"] & fd["ok"]
+    assert both.mean() > 0.9 and np.array_equal(ana["ok"], fd["ok"])
+    scale = np.maximum(1.0, np.abs(ana["y"][both]).max(axis=1))[:, None]
+    assert np.all(np.abs(fd["y"][both] - ana["y"][both]) <= 1e-8 * scale)
+    assert np.mean(np.all(fd["k"] == ana["k"], axis=1)) > 0.99
+    assert np.all(np.abs(fd["k"] - ana["k"]) <= 1)
+    assert np.all(fd["iters"][both] <= ana["iters"][both] + 2)
+
+
 def test_implicit_newton_failure_is_reported(orc):
     net = W.dimer()
     res = orc.implicit(net.m, net.p, net.theta, [1000, 10, 0], 0.01, [10, 5, 0, 0], -1,
