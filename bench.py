@@ -36,6 +36,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 WORKLOADS = {
     "dimer": "dimer_workload",
     "birth_death": "birth_death_workload",
+    "dimer_rathinam": "rathinam_workload",    # implicit leaps (Jacobian variants via --options)
     "random48x128": "random_network_workload",
     "mixed_set": "mixed_set_workload",        # three networks in one launch (lx_simulate_set)
     "telegraph_pf": "telegraph_workload",     # the particle-filter interval loop (lx_pf_*)
@@ -66,6 +67,9 @@ def parse():
                     help="override the workload's t_end (secondary workloads only)")
     ap.add_argument("--options", default="",
                     help="JSON object of lx options applied to every form (knob exploration)")
+    ap.add_argument("--times", type=int, default=0,
+                    help="record the states at this many evenly spaced observation times "
+                         "(lx_simulate_grid) instead of only at t_end")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="trajectories the oracle baseline runs (default: all for the dimer, "
                          "1024 otherwise)")
@@ -135,9 +139,14 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
     if args.options:
         opts.update(json.loads(args.options))
     stream = torch.cuda.current_stream()
+    grid_times = observation_times(torch, args, wl)
 
     def launch():
-        lx.simulate(h, theta, x0, wl.t_end, wl.eps, wl.mode, out=out, stream=stream, **opts)
+        if grid_times is None:
+            lx.simulate(h, theta, x0, wl.t_end, wl.eps, wl.mode, out=out, stream=stream, **opts)
+        else:
+            lx.simulate_grid(h, theta, x0, grid_times, wl.eps, wl.mode, out=out, stream=stream,
+                             **opts)
 
     for _ in range(args.warmup):
         launch()
@@ -156,7 +165,7 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
     r_total = int(out["r"].sum(dtype=torch.int64).item())
     stats = lx.stats_numpy(out["stats"])
     return {
-        "kernel_id": kernel_id(opts),
+        "kernel_id": kernel_id(dict(opts, observation_times=args.times) if args.times else opts),
         "ms_per_step": ms,
         "wall_s": wall,
         "trajectories_per_s": wl.P / (ms / 1e3),
@@ -168,6 +177,15 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
         "schedule": opts["schedule"],
         "options": {k: v for k, v in opts.items() if k not in ("precision", "schedule")},
     }
+
+
+def observation_times(torch, args, wl):
+    """--times K: K evenly spaced times ending at t_end (device tensor), or None."""
+    if not args.times:
+        return None
+    import numpy as np
+    return torch.as_tensor(np.linspace(wl.t_end / args.times, wl.t_end, args.times),
+                           device="cuda")
 
 
 def timed(args, torch, launch, stream):
@@ -339,6 +357,8 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.times and args.workload in ("mixed_set", "telegraph_pf"):
+        raise SystemExit("--times applies to single-network workloads")
     if args.workload == "mixed_set":
         return bench_set(args, torch, lx, W)
     if args.workload == "telegraph_pf":
@@ -361,6 +381,9 @@ def main():
             "G": torch.empty((wl.P, net.M), dtype=torch.float64, device="cuda"),
             "stats": torch.empty((wl.P, lx.STATS_WORDS), dtype=torch.int64, device="cuda"),
         }
+        if args.times:
+            out["x_grid"] = torch.empty((wl.P, args.times, net.N), dtype=torch.int32,
+                                        device="cuda")
         try:
             results[form] = time_form(args, lx, h, theta, x0, wl, form, out)
         except lx.LxError as exc:
@@ -381,8 +404,14 @@ def main():
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
         t0 = time.perf_counter()
         n_cpu = args.cpu_sample or (wl.P if args.workload == "dimer" else min(wl.P, 1024))
-        ref = oracle.simulate(net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu], wl.t_end,
-                              mode=wl.mode, nthreads=nth)
+        if args.times:
+            import numpy as np
+            ref = oracle.simulate_grid(net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu],
+                                       np.linspace(wl.t_end / args.times, wl.t_end, args.times),
+                                       mode=wl.mode, nthreads=nth)
+        else:
+            ref = oracle.simulate(net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu], wl.t_end,
+                                  mode=wl.mode, nthreads=nth)
         dt = time.perf_counter() - t0
         ops_per_traj = float(ref["stats"]["ops"].mean())
         what = (f"all {wl.P} trajectories of the workload" if n_cpu == wl.P else
@@ -427,6 +456,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if args.times:
+        line["config"]["observation_times"] = args.times
     print(json.dumps(line), flush=True)
 
 

@@ -67,6 +67,10 @@ typedef int32_t lx_status;
                               with 16 or 32 active lanes when the ensemble is too
                               small to give every SIMD a full wave */
 
+/* Jacobian of the implicit solve (lx_options.jacobian). */
+#define LX_JAC_ANALYTIC 0
+#define LX_JAC_FD 1
+
 /* Per-trajectory status codes (lx_stats.status). */
 #define LX_LANE_OK 0
 #define LX_LANE_STEP_BUDGET 1     /* max_steps attempts used before t_end */
@@ -111,7 +115,12 @@ typedef struct lx_options {
                            trajectory split its Poisson draws and upcoming SSA draws;
                            lanes_per_wave counts lanes, so a wave holds
                            lanes_per_wave / lanes_per_traj trajectories */
-  int32_t reserved[4];
+  int32_t jacobian;     /* Jacobian of the implicit solve: LX_JAC_ANALYTIC (0, default,
+                           the exact mass-action derivative, which is what a symbolic
+                           Jacobian gives) or LX_JAC_FD (1, forward differences with the
+                           step 2^-26 max(|y_k|, 1): the numerically estimated Jacobian
+                           (Background section) */
+  int32_t reserved[3];
 } lx_options;
 
 /* Per-trajectory statistics (80 bytes). */
@@ -194,6 +203,30 @@ lx_status lx_simulate(lx_network net, int64_t P, const double* theta, const int3
                       double t_end, double eps, int32_t mode, const lx_options* opt,
                       int32_t* x_out, int32_t* r_out, double* G_out, lx_stats* stats,
                       void* stream);
+
+/* lx_simulate with observation times: the trajectories also stop at each of
+ * times[0..n_times) and their states there are written out (the paper
+ * measures accuracy on species distributions at fixed time points, Results
+ * section).  A trajectory stops at an observation time as it stops at t_end
+ * (a leap is shortened to end there and no critical reaction fires; an SSA
+ * step whose waiting time passes it integrates g up to it and does not fire;
+ * an absorbing state integrates g up to it), records its state, and goes on
+ * from there with fresh step decisions and the same random stream.  The
+ * simulation ends at times[n_times - 1].
+ *   times   device double [n_times]: non-decreasing, from opt->t_start, finite.
+ *           A trajectory meeting a time below its current time, or not
+ *           finite, ends with status LX_LANE_BAD_INPUT.
+ *   x_grid  device int32 [P][n_times][N]: X(times[k]); -1 in every row whose
+ *           time the trajectory did not reach with status OK.
+ *   other arguments as lx_simulate; x_out, r_out, G_out and stats describe
+ *   the end of the simulation (or where the trajectory stopped).
+ * n_times = 1 with times[0] = t_end gives exactly lx_simulate's results.
+ * Errors as lx_simulate, and LX_E_INVALID for n_times < 1 or a null times /
+ * x_grid pointer with P > 0. */
+lx_status lx_simulate_grid(lx_network net, int64_t P, const double* theta, const int32_t* x0,
+                           int32_t n_times, const double* times, double eps, int32_t mode,
+                           const lx_options* opt, int32_t* x_grid, int32_t* x_out,
+                           int32_t* r_out, double* G_out, lx_stats* stats, void* stream);
 
 /* One network of a multi-network simulation. */
 typedef struct lx_set_item {

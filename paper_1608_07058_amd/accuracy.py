@@ -1,0 +1,221 @@
+"""Accuracy of the leaping methods against exact SSA.
+
+The paper measures accuracy as the Kullback-Leibler divergence between the
+species distributions of the method and of exact SSA at fixed time points,
+averaged over time points and species, from 10^4 simulations and 5
+replicates at eps = 0.03 (Results section and its accuracy table).  This
+module computes that measure from ensembles simulated with
+``lx.simulate_grid``: the reference is the library's SSA mode (Gillespie's
+direct method, identical trajectory by trajectory to the oracle's SSA), the
+methods under test are the adaptive and explicit leaping forms in either
+precision policy, and a second, independent SSA ensemble gives the floor
+that sampling noise alone produces.
+
+Reading of the estimator (the paper does not give its binning): at one time
+and species the two samples share integer-aligned bins spanning their
+pooled range -- one bin per copy number when the range holds at most
+``MAX_BINS`` values, else bins of equal integer width, at most ``MAX_BINS``
+of them; each histogram gets half a count per bin so that no bin is empty,
+and KL(p_ref || p_test) = sum_b p_ref(b) log(p_ref(b) / p_test(b)).
+
+    python -m paper_1608_07058_amd.accuracy --out accuracy.md
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+MAX_BINS = 32
+
+
+def kl_divergence(ref, test, max_bins: int = MAX_BINS) -> float:
+    """KL(p_ref || p_test) between the binned empirical distributions of two
+    integer samples (see the module docstring for the binning)."""
+    a = np.asarray(ref, dtype=np.int64).ravel()
+    b = np.asarray(test, dtype=np.int64).ravel()
+    if a.size == 0 or b.size == 0:
+        raise ValueError("empty sample")
+    lo = min(a.min(), b.min())
+    span = int(max(a.max(), b.max()) - lo + 1)
+    if span == 1:
+        return 0.0
+    width = -(-span // max_bins)
+    nb = -(-span // width)
+    ca = np.bincount((a - lo) // width, minlength=nb).astype(np.float64)
+    cb = np.bincount((b - lo) // width, minlength=nb).astype(np.float64)
+    p = (ca + 0.5) / (a.size + 0.5 * nb)
+    q = (cb + 0.5) / (b.size + 0.5 * nb)
+    return float(np.sum(p * np.log(p / q)))
+
+
+def kl_matrix(ref_grid, test_grid, max_bins: int = MAX_BINS) -> np.ndarray:
+    """KL divergence at every observation time and species, [K][N], of two
+    ensembles of states x_grid [P][K][N]."""
+    ref_grid = np.asarray(ref_grid)
+    test_grid = np.asarray(test_grid)
+    if ref_grid.ndim != 3 or test_grid.ndim != 3 or ref_grid.shape[1:] != test_grid.shape[1:]:
+        raise ValueError("need two [P][K][N] arrays with the same K and N")
+    if (ref_grid < 0).any() or (test_grid < 0).any():
+        raise ValueError("a trajectory did not reach every observation time")
+    K, N = ref_grid.shape[1:]
+    return np.array([[kl_divergence(ref_grid[:, k, i], test_grid[:, k, i], max_bins)
+                      for i in range(N)] for k in range(K)])
+
+
+def mean_kl(ref_grid, test_grid, max_bins: int = MAX_BINS) -> float:
+    """KL divergence averaged over observation times and species."""
+    return float(np.mean(kl_matrix(ref_grid, test_grid, max_bins)))
+
+
+def variance_ratio(ref_grid, test_grid) -> np.ndarray:
+    """Per species, the ratio of the method's variance to the reference's,
+    averaged over the observation times where the reference varies."""
+    vr = np.var(np.asarray(ref_grid, np.float64), axis=0)
+    vt = np.var(np.asarray(test_grid, np.float64), axis=0)
+    out = []
+    for i in range(vr.shape[1]):
+        ok = vr[:, i] > 0
+        out.append(float(np.mean(vt[ok, i] / vr[ok, i])) if ok.any() else 1.0)
+    return np.array(out)
+
+
+# name -> (factory in workloads, t_end): horizons at which exact SSA of 10^4
+# trajectories takes seconds
+NETWORKS = {
+    "birth_death": ("birth_death", 100.0),
+    "isomerisation": ("isomerisation", 5.0),
+    "dimer": ("dimer", 30.0),
+    "dimer_rathinam": ("dimer_rathinam", 2.0),
+    "schlogl": ("schlogl", 20.0),
+    "telegraph": ("telegraph", 50.0),
+}
+
+METHODS = {
+    # label -> (mode, precision)
+    "adaptive, mixed": ("adaptive", "mixed"),
+    "adaptive, fp64": ("adaptive", "fp64"),
+    "explicit, mixed": ("explicit", "mixed"),
+}
+
+SEED_REF, SEED_FLOOR, SEED_TEST = 11, 22, 33
+
+
+def run_network(lx, net, t_end, *, P=10000, replicates=5, n_times=20, eps=0.03,
+                methods=METHODS, log=None):
+    """Mean and standard deviation over replicates of the mean KL divergence
+    of each method (and of a second SSA ensemble) against exact SSA, and the
+    median over replicates of the ensemble's time per trajectory (launch
+    bracketed by HIP events).  Replicate k uses random stream k."""
+    import torch
+    from paper_1608_07058_amd import workloads as W
+
+    h = lx.Network(net.m, net.p)
+    theta, x0 = W.tile(net, P)
+    th = torch.as_tensor(theta, device="cuda")
+    xi = torch.as_tensor(x0, device="cuda")
+    times = torch.as_tensor(np.linspace(t_end / n_times, t_end, n_times), device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def grid(mode, precision, seed, k):
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        out = lx.simulate_grid(h, th, xi, times, eps, mode, precision=precision,
+                               schedule="batched", seed=seed, rng_stream=k, stream=stream)
+        end.record(stream)
+        torch.cuda.synchronize()
+        st = lx.stats_numpy(out["stats"])
+        if not (st["status"] == 0).all():
+            raise RuntimeError(f"{net.name} {mode}/{precision}: lanes failed")
+        return out["x_grid"].cpu().numpy(), start.elapsed_time(end) / P * 1e-3
+
+    # one untimed call per configuration: the first call of a kernel variant
+    # includes its run-time compilation
+    grid("ssa", "fp64", SEED_REF, replicates)
+    for mode, precision in methods.values():
+        grid(mode, precision, SEED_TEST, replicates)
+
+    rows = {}
+    kl = {label: [] for label in ["SSA (independent)", *methods]}
+    secs = {label: [] for label in kl}
+    per_species = {label: [] for label in kl}
+    vratio = {label: [] for label in kl}
+    for k in range(replicates):
+        ref, t_ref = grid("ssa", "fp64", SEED_REF, k)
+        runs = {"SSA (independent)": grid("ssa", "fp64", SEED_FLOOR, k)}
+        for label, (mode, precision) in methods.items():
+            runs[label] = grid(mode, precision, SEED_TEST, k)
+        for label, (test, secs_per) in runs.items():
+            km = kl_matrix(ref, test)
+            kl[label].append(float(km.mean()))
+            per_species[label].append(km.mean(axis=0))
+            vratio[label].append(variance_ratio(ref, test))
+            secs[label].append(secs_per)
+        if log:
+            log(f"{net.name} replicate {k}: " +
+                ", ".join(f"{lab} {v[-1]:.4f}" for lab, v in kl.items()))
+    for label in kl:
+        rows[label] = {"kl_mean": float(np.mean(kl[label])), "kl_std": float(np.std(kl[label])),
+                       "s_per_trajectory": float(np.median(secs[label])),
+                       "kl_per_species": np.mean(per_species[label], axis=0).tolist(),
+                       "variance_ratio_per_species": np.mean(vratio[label], axis=0).tolist()}
+    h.close()
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--networks", default=",".join(NETWORKS))
+    ap.add_argument("--P", type=int, default=10000)
+    ap.add_argument("--replicates", type=int, default=5)
+    ap.add_argument("--times", type=int, default=20)
+    ap.add_argument("--out", default=None, help="write a markdown table here")
+    args = ap.parse_args()
+    from paper_1608_07058_amd import lx, workloads as W
+    lx.lib()
+    results = {}
+    for name in args.networks.split(","):
+        factory, t_end = NETWORKS[name]
+        net = getattr(W, factory)()
+        t0 = time.perf_counter()
+        results[name] = run_network(lx, net, t_end, P=args.P, replicates=args.replicates,
+                                    n_times=args.times,
+                                    log=lambda s: print(s, file=sys.stderr, flush=True))
+        print(f"{name}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    print(json.dumps(results))
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(table_markdown(results, args))
+
+
+def table_markdown(results, args) -> str:
+    labels = list(next(iter(results.values())))
+    lines = [f"KL divergence to exact SSA, mean over {args.times} observation times and all "
+             f"species (std over {args.replicates} replicates), {args.P} trajectories each, "
+             f"eps 0.03; kernel time per trajectory in microseconds.", "",
+             "| network | " + " | ".join(labels) + " |",
+             "|---|" + "---|" * len(labels)]
+    for name, rows in results.items():
+        cells = [f"{rows[l]['kl_mean']:.4f} ± {rows[l]['kl_std']:.4f} "
+                 f"({rows[l]['s_per_trajectory'] * 1e6:.3g} µs)" for l in labels]
+        lines.append(f"| {name} (t_end {NETWORKS[name][1]:g}) | " + " | ".join(cells) + " |")
+    lines += ["", "Per species: KL divergence (mean over times) / variance relative to SSA "
+              "(mean over times).", "",
+              "| network | species | " + " | ".join(labels) + " |",
+              "|---|---|" + "---|" * len(labels)]
+    for name, rows in results.items():
+        n_species = len(rows[labels[0]]["kl_per_species"])
+        for i in range(n_species):
+            cells = [f"{rows[l]['kl_per_species'][i]:.4f} / {rows[l]['variance_ratio_per_species'][i]:.2f}"
+                     for l in labels]
+            lines.append(f"| {name} | {i} | " + " | ".join(cells) + " |")
+    return "\n".join(lines) + "\n"
+
+
+if __name__ == "__main__":
+    main()

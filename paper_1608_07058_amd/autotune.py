@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_FILE = os.path.join(HERE, "tuned.json")
 
 GRID = {
-    "lanes_per_traj": (1, 2, 4, 8),
+    "lanes_per_traj": (1, 2, 4, 8, 16),
     "lanes_per_wave": (16, 32, 64),
     "ssa_k": (4, 8, 16),
     "block_size": (64, 256),

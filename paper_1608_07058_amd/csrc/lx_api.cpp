@@ -277,20 +277,21 @@ std::string const_source(const lx::SimParams& p) {
            "      lam_thr = %a, newton_tol = %a;\n"
            "  static constexpr long long max_steps = %lldLL;\n"
            "  static constexpr int n_c = %d, n_ssa_ex = %d, n_ssa_im = %d, newton_maxit = %d,\n"
-           "      kcap = %d, mode = %d, accumulate = %d, ssa_k = %d, regroup = %d;\n"
+           "      kcap = %d, mode = %d, accumulate = %d, ssa_k = %d, regroup = %d, jacobian = %d;\n"
            "};\n",
            p.eps, p.delta, p.n_stiff, p.k_ssa, p.k_crit, p.lam_thr, p.newton_tol, p.max_steps,
            p.n_c, p.n_ssa_ex, p.n_ssa_im, p.newton_maxit, p.kcap, p.mode, p.accumulate, p.ssa_k,
-           p.regroup);
+           p.regroup, p.jacobian);
   return buf;
 }
 
 // Full hipRTC source of one kernel variant of a network; `consts` is
 // const_source() of the launch, or empty for run-time constants (hooks).
 std::string kernel_source(const lx_network_s& net, const char* variant, int precision, int block,
-                          int tpl, const std::string& consts) {
+                          int tpl, const std::string& consts, bool grid = false) {
   std::ostringstream src;
   src << "// generated by liblx\n";
+  if (grid) src << "#define LX_GRID 1\n";
   src << "#define LX_TPL " << tpl << "\n";
   src << "#define LX_POLICY " << (precision == LX_PREC_MIXED ? "lx::Mixed" : "lx::F64") << "\n";
   src << "#define LX_BLOCK " << block << "\n";
@@ -381,13 +382,15 @@ lx_status get_kernel_src(lx_network_s* owner, const std::string& variant_key, F 
 }
 
 lx_status get_kernel(lx_network_s* net, const char* variant, int precision, int block,
-                     const char* fname, hipFunction_t* fn, int tpl, const std::string& consts) {
+                     const char* fname, hipFunction_t* fn, int tpl, const std::string& consts,
+                     bool grid = false) {
   std::ostringstream key;
-  key << variant << "/" << precision << "/" << block << "/tpl" << tpl << "/c" << std::hex
-      << fnv1a(consts) << std::dec;
+  key << variant << (grid ? "-grid" : "") << "/" << precision << "/" << block << "/tpl" << tpl
+      << "/c" << std::hex << fnv1a(consts) << std::dec;
   return get_kernel_src(
-      net, key.str(), [&]() { return kernel_source(*net, variant, precision, block, tpl, consts); },
-      fname, fn);
+      net, key.str(),
+      [&]() { return kernel_source(*net, variant, precision, block, tpl, consts, grid); }, fname,
+      fn);
 }
 
 // Schedule-dependent fields of the launch parameters in canonical form (they
@@ -453,6 +456,8 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
     return fail(LX_E_INVALID, "lanes_per_wave must be at least lanes_per_traj");
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 8)
     return fail(LX_E_INVALID, "blocks_per_cu must be in [0, 8]");
+  if (o.jacobian != LX_JAC_ANALYTIC && o.jacobian != LX_JAC_FD)
+    return fail(LX_E_INVALID, "jacobian must be LX_JAC_ANALYTIC or LX_JAC_FD");
   {
     const uint64_t stride = o.pid_stride ? o.pid_stride : 1;
     if (P > 0 && (uint64_t)o.pid_base + (uint64_t)(P - 1) * stride >= 4294967296ull)
@@ -481,6 +486,7 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
   prm->kcap = 20 + 4 * (int)std::ceil(o.lambda_thr);
   prm->mode = mode;
   prm->accumulate = o.accumulate ? 1 : 0;
+  prm->jacobian = o.jacobian;
   return LX_OK;
 }
 
@@ -494,7 +500,7 @@ struct SimLaunch {
 };
 
 lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end, double eps,
-                   int32_t mode, SimLaunch* L) {
+                   int32_t mode, SimLaunch* L, bool grid = false) {
   lx_status st = fill_params(o, P, t_end, eps, mode, &L->prm);
   if (st != LX_OK) return st;
   if (P == 0) return LX_OK;
@@ -510,7 +516,7 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
     L->block = o.block_size ? o.block_size : (batched ? 256 : 64);
     finish_params(o, true, &L->prm);
     st = get_kernel(net, "large", o.precision, L->block, "lx_sim_large", &L->fn, 1,
-                    const_source(L->prm));
+                    const_source(L->prm), grid);
     if (st != LX_OK) return st;
     long long per_block = L->block;
     int lanes = 64;
@@ -535,7 +541,7 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
   finish_params(o, L->batched, &L->prm);
   st = get_kernel(net, L->batched ? "batched" : "plain", o.precision, L->block,
                   L->batched ? "lx_sim_batched" : "lx_sim_plain", &L->fn,
-                  L->batched ? tpl_of(o) : 1, const_source(L->prm));
+                  L->batched ? tpl_of(o) : 1, const_source(L->prm), grid);
   if (st != LX_OK) return st;
   L->grid = (P + L->block - 1) / L->block;
   if (L->batched) {
@@ -564,8 +570,7 @@ lx_status launch_sim(const SimLaunch& L, const lx::SimParams& prm, const double*
                   (void*)&G_out, (void*)&sp, (void*)&p};
   hipError_t e = hipModuleLaunchKernel(L.fn, (unsigned)L.grid, 1, 1, (unsigned)L.block, 1, 1, 0,
                                        s, args, nullptr);
-  if (e != hipSuccess)
-    return hip_fail(e, L.batched ? "launch lx_sim_batched" : "launch lx_sim_plain");
+  if (e != hipSuccess) return hip_fail(e, "launch of the simulation kernel");
   return LX_OK;
 }
 
@@ -727,6 +732,34 @@ lx_status lx_simulate(lx_network net, int64_t P, const double* theta, const int3
   SimLaunch L;
   st = plan_sim(net, P, o, t_end, eps, mode, &L);
   if (st != LX_OK) return st;
+  return launch_sim(L, L.prm, theta, x0, x_out, r_out, G_out, stats, (hipStream_t)stream);
+}
+
+lx_status lx_simulate_grid(lx_network net, int64_t P, const double* theta, const int32_t* x0,
+                           int32_t n_times, const double* times, double eps, int32_t mode,
+                           const lx_options* opt, int32_t* x_grid, int32_t* x_out,
+                           int32_t* r_out, double* G_out, lx_stats* stats, void* stream) {
+  if (!net) return fail(LX_E_INVALID, "null network");
+  if (P < 0) return fail(LX_E_INVALID, "P < 0");
+  if (n_times < 1) return fail(LX_E_INVALID, "need n_times >= 1");
+  lx_options o;
+  if (opt) o = *opt;
+  else lx_options_default(&o);
+  // the end of the simulation is times[n_times - 1], checked per trajectory
+  lx::SimParams tmp;
+  lx_status st = fill_params(o, P, o.t_start, eps, mode, &tmp);
+  if (st != LX_OK) return st;
+  if (P == 0) return LX_OK;
+  if (!theta || !x0 || !times || !x_grid || !x_out || !r_out || !G_out)
+    return fail(LX_E_INVALID, "null input/output pointer");
+  if ((long long)n_times > (1LL << 62) / ((long long)P * net->N))
+    return fail(LX_E_INVALID, "x_grid too large");
+  SimLaunch L;
+  st = plan_sim(net, P, o, o.t_start, eps, mode, &L, true);
+  if (st != LX_OK) return st;
+  L.prm.times = times;
+  L.prm.x_grid = x_grid;
+  L.prm.n_times = n_times;
   return launch_sim(L, L.prm, theta, x0, x_out, r_out, G_out, stats, (hipStream_t)stream);
 }
 

@@ -23,11 +23,17 @@ struct SimParams {
   long long P;
   unsigned int k0, k1, pid_base, pid_stride;
   int n_c, n_ssa_ex, n_ssa_im, newton_maxit, kcap, mode, accumulate;
+  int jacobian;           // implicit solve: 0 analytic Jacobian, 1 forward differences
   // batched scheduler
   long long per_block;    // particles owned by each block (contiguous range)
   int lanes;              // active lanes per wave (4 to 64)
   int ssa_k;              // SSA steps a lane in an SSA burst takes per leap iteration
   int regroup;            // regroup lanes by next action every `regroup` iterations (0: never)
+  // observation times (kernels compiled with LX_GRID): the state at
+  // times[k], k < n_times, goes to x_grid [P][n_times][N]
+  const double* times;
+  int* x_grid;
+  int n_times;
 };
 
 // Per-trajectory statistics (layout of the public lx_stats).

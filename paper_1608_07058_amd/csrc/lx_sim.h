@@ -48,6 +48,26 @@ __device__ __forceinline__ void g_all(const double (&y)[NET::N], double (&g)[NET
   }
 }
 
+// g_j(y) with y_k replaced by yk (a forward-difference evaluation).
+template <class NET>
+__device__ __forceinline__ double g_moved(int j, int k, const double (&y)[NET::N], double yk) {
+  double gj = 1.0;
+#pragma unroll
+  for (int i = 0; i < NET::N; ++i)
+    if (NET::RO[j][i] > 0) gj = gj * binom_real(i == k ? yk : y[i], NET::RO[j][i]);
+  return gj;
+}
+
+// Forward-difference step of species k at y: the step 2^-26 max(|y_k|, 1)
+// (square root of the binary64 epsilon, scaled), taken as the representable
+// difference (y_k + step) - y_k; returns the moved coordinate in *yh.
+__device__ __forceinline__ double fd_step(double yk, double* yh) {
+  const double ak = __builtin_fabs(yk);
+  const double step = 0x1p-26 * (ak < 1.0 ? 1.0 : ak);
+  *yh = yk + step;
+  return *yh - yk;
+}
+
 // d g_j / d y_k.
 template <class NET>
 __device__ __forceinline__ double dg_of(int j, int k, const double (&y)[NET::N]) {
@@ -70,8 +90,9 @@ __device__ __forceinline__ T group_read(T v, int s) {
 // that hold identical state and run identical control flow; they split the
 // Poisson draws of a leap (one reaction each) and the draws of upcoming SSA
 // steps (one attempt each) and exchange the results, so every value is the
-// one the single-lane form computes.
-template <class P, class NET, int TPL = 1>
+// one the single-lane form computes.  With GRID the trajectory also stops at
+// observation times (prm.times) and records its state there (grid_next).
+template <class P, class NET, int TPL = 1, bool GRID = false>
 struct Lane {
   typedef typename P::R R;
   static constexpr int N = NET::N;
@@ -88,6 +109,8 @@ struct Lane {
   double t;
   u32 e;
   int status;
+  double tend;  // end of the current stretch: the next observation time (GRID)
+  int kt;       // index of that time (GRID)
   // step state
   double g[M];
   R a[M];
@@ -100,8 +123,14 @@ struct Lane {
   u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip;  // < 2^32: attempts are bounded by max_steps
   long long n_nit;
 
+  // The time the trajectory runs to now: t_end, or the next observation time.
+  __device__ __forceinline__ double t_end_(const SimParams& prm) const {
+    if constexpr (GRID) return tend;
+    else return prm.t_end;
+  }
+
   __device__ __forceinline__ bool active(const SimParams& prm) const {
-    return (status == LANE_OK) & (t < prm.t_end);  // no short circuit: one condition
+    return (status == LANE_OK) & (t < t_end_(prm));  // no short circuit: one condition
   }
 
   __device__ __forceinline__ void load(long long p, const double* __restrict__ theta,
@@ -124,6 +153,11 @@ struct Lane {
     }
     status = bad ? LANE_BAD_INPUT : LANE_OK;
     t = prm.t_start;
+    if constexpr (GRID) {
+      kt = 0;
+      tend = prm.times[0];
+      if (!(tend >= t) || tend == LX_INF_F64) status = LANE_BAD_INPUT;
+    }
     e = 0;
     plan = false;
     gvalid = false;
@@ -158,8 +192,43 @@ struct Lane {
     }
   }
 
+  // Observation times: called when the lane has stopped, at its current
+  // time tend (status OK) or for good.  Records the state as row kt of
+  // x_grid [P][n_times][N] (-1 where the time was not reached in status OK;
+  // only `writer` stores) and opens the stretch to the next time, with fresh
+  // step decisions and the same random stream.  A next time below the
+  // current one, or not finite, ends the trajectory with BAD_INPUT.  Returns
+  // true if the trajectory goes on.
+  __device__ __forceinline__ bool grid_next(long long p, const SimParams& prm, bool writer) {
+    const bool ok = status == LANE_OK;
+    int* row = prm.x_grid + ((long long)p * prm.n_times + kt) * N;
+    if (writer) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) row[i] = ok ? x[i] : -1;
+    }
+    kt += 1;
+    if (ok && kt < prm.n_times) {
+      const double tn = prm.times[kt];
+      if ((tn >= t) & (tn != LX_INF_F64)) {
+        tend = tn;
+        ssa_left = 0;
+        plan = false;
+        return true;
+      }
+      status = LANE_BAD_INPUT;
+    }
+    if (writer) {
+      for (int k = kt; k < prm.n_times; ++k) {
+        row += N;
+#pragma unroll
+        for (int i = 0; i < N; ++i) row[i] = -1;
+      }
+    }
+    return false;
+  }
+
   // Number of 32-bit words of the state moved when lanes are regrouped.
-  static constexpr int STATE_WORDS = 20 + N + 3 * M;
+  static constexpr int STATE_WORDS = 20 + N + 3 * M + (GRID ? 3 : 0);
 
   // Write the trajectory's state to an LDS slot (regrouping).  theta, g, a
   // and the plan's masks are not moved: they are reloaded or recomputed.
@@ -197,6 +266,12 @@ struct Lane {
     w[q++] = n_clip;
     w[q++] = (u32)n_nit;
     w[q++] = (u32)((unsigned long long)n_nit >> 32);
+    if constexpr (GRID) {
+      const unsigned long long eb = __builtin_bit_cast(unsigned long long, tend);
+      w[q++] = (u32)eb;
+      w[q++] = (u32)(eb >> 32);
+      w[q++] = (u32)kt;
+    }
   }
 
   // Read a state written by save(); theta is reloaded from the input, the
@@ -235,6 +310,13 @@ struct Lane {
     n_nfail = w[q++];
     n_clip = w[q++];
     n_nit = (long long)((unsigned long long)w[q] | ((unsigned long long)w[q + 1] << 32));
+    if constexpr (GRID) {
+      q += 2;
+      const unsigned long long eb = (unsigned long long)w[q] | ((unsigned long long)w[q + 1] << 32);
+      q += 2;
+      tend = __builtin_bit_cast(double, eb);
+      kt = (int)w[q++];
+    }
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       th[j] = theta[p * M + j];
@@ -373,10 +455,10 @@ struct Lane {
   }
 
   __device__ __forceinline__ void absorb(const SimParams& prm) {
-    const double rem = prm.t_end - t;
+    const double rem = t_end_(prm) - t;
 #pragma unroll
     for (int j = 0; j < M; ++j) G[j] = G[j] + g[j] * rem;
-    t = prm.t_end;
+    t = t_end_(prm);
   }
 
   // One SSA step (Gillespie 1977 direct method) with exact G.
@@ -400,7 +482,7 @@ struct Lane {
     n_ssa += stepping ? 1u : 0u;
     status = budget ? (int)LANE_STEP_BUDGET : status;
     const double tau_s = (double)(E / a0);  // +inf when a0 = 0 (E > 0)
-    const double rem = prm.t_end - t;
+    const double rem = t_end_(prm) - t;
     const bool past = tau_s >= rem;
     const bool absorbing = zero || (stepping && past);
     const bool fire = stepping && !past;
@@ -440,7 +522,7 @@ struct Lane {
     }
 #pragma unroll
     for (int j = 0; j < M; ++j) r[j] = r[j] + (j == jf ? 1 : 0);
-    t = absorbing ? prm.t_end : (fire ? t + tau_s : t);
+    t = absorbing ? t_end_(prm) : (fire ? t + tau_s : t);
     gvalid = fire ? false : gvalid;
   }
 
@@ -534,6 +616,13 @@ struct Lane {
           if (NET::NU[j][i] != 0 && ((ncr >> j) & 1u)) s = s + (double)NET::NU[j][i] * ay[j];
         b[i] = -((y[i] - c[i]) - tau * s);
       }
+      // d a_j / d y_k: analytic, or forward differences (a_j re-evaluated with
+      // y_k moved by the representable step h_k)
+      double yh[N], h[N];
+      if (LXP(prm, jacobian)) {
+#pragma unroll
+        for (int kk = 0; kk < N; ++kk) h[kk] = fd_step(y[kk], &yh[kk]);
+      }
 #pragma unroll
       for (int i = 0; i < N; ++i) {
 #pragma unroll
@@ -542,7 +631,12 @@ struct Lane {
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             if (NET::NU[j][i] == 0 || NET::RO[j][kk] == 0) continue;
-            if ((ncr >> j) & 1u) s = s + (double)NET::NU[j][i] * (th[j] * dg_of<NET>(j, kk, y));
+            if ((ncr >> j) & 1u) {
+              const double d = LXP(prm, jacobian)
+                                   ? (th[j] * g_moved<NET>(j, kk, y, yh[kk]) - ay[j]) / h[kk]
+                                   : th[j] * dg_of<NET>(j, kk, y);
+              s = s + (double)NET::NU[j][i] * d;
+            }
           }
           A[i][kk] = (i == kk ? 1.0 : 0.0) - tau * s;
         }
@@ -621,7 +715,7 @@ struct Lane {
       jc = found ? jc : jlast;
     }
     double tau = (double)tau_r;
-    const double rem = prm.t_end - t;
+    const double rem = t_end_(prm) - t;
     bool last = false;
     if (tau >= rem) {
       tau = rem;
@@ -726,7 +820,7 @@ struct Lane {
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) x[i] = (int)xn[i];
-    t = last ? prm.t_end : t + tau;
+    t = last ? t_end_(prm) : t + tau;
     if (implicit) n_im += 1;
     else n_ex += 1;
     plan = false;
@@ -832,6 +926,11 @@ struct Lane {
 #ifndef LX_TPL
 #define LX_TPL 1
 #endif
+#ifdef LX_GRID
+#define LX_GRID_ON true
+#else
+#define LX_GRID_ON false
+#endif
 
 }  // namespace lx
 
@@ -843,9 +942,15 @@ extern "C" __global__ void __launch_bounds__(LX_BLOCK)
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= prm.P) return;
   const lx::Key key{prm.k0, prm.k1};
-  lx::Lane<LX_POLICY, LxNet> lane;
+  lx::Lane<LX_POLICY, LxNet, 1, LX_GRID_ON> lane;
   lane.load(p, theta, x0, r_out, G_out, prm);
-  while (lane.active(prm)) lane.step(prm, key);
+  for (;;) {
+    while (lane.active(prm)) lane.step(prm, key);
+    if constexpr (LX_GRID_ON) {
+      if (lane.grid_next(p, prm, true)) continue;
+    }
+    break;
+  }
   lane.store(p, x_out, r_out, G_out, stats);
 }
 #endif
@@ -879,7 +984,7 @@ __device__ __forceinline__ void run_batched(long long blk, const double* __restr
   const Key key{prm.k0, prm.k1};
   long long p = lo + (long long)wave * prm.lanes + slot;
   bool has = slot < prm.lanes && p < hi;
-  Lane<LX_POLICY, NET, TPL> lane;
+  Lane<LX_POLICY, NET, TPL, LX_GRID_ON> lane;
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
   while (has) {
     if (lane.active(prm)) {
@@ -887,6 +992,9 @@ __device__ __forceinline__ void run_batched(long long blk, const double* __restr
       if (lane.active(prm) && !lane.in_ssa(prm)) lane.step(prm, key);
     }
     if (!lane.active(prm)) {
+      if constexpr (LX_GRID_ON) {
+        if (lane.grid_next(p, prm, sub == 0)) continue;
+      }
       if (sub == 0) lane.store(p, x_out, r_out, G_out, stats);
       long long pn = 0;
       if (sub == 0) pn = (long long)atomicAdd(next, 1ull);
@@ -911,7 +1019,7 @@ __device__ __forceinline__ void run_regroup(long long blk, const double* __restr
                                             const int* __restrict__ x0, int* x_out, int* r_out,
                                             double* G_out, Stats* stats, const SimParams& prm,
                                             unsigned long long* next) {
-  typedef Lane<LX_POLICY, NET> LaneT;
+  typedef Lane<LX_POLICY, NET, 1, LX_GRID_ON> LaneT;
   constexpr int STRIDE = LaneT::STATE_WORDS;
   __shared__ u32 slots[LX_BLOCK * STRIDE];
   __shared__ int counts[2 * (LX_BLOCK / 64)];
@@ -932,6 +1040,9 @@ __device__ __forceinline__ void run_regroup(long long blk, const double* __restr
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
   for (int iter = 0;; ++iter) {
     while (has && !lane.active(prm)) {  // store finished trajectories, refill
+      if constexpr (LX_GRID_ON) {
+        if (lane.grid_next(p, prm, true)) continue;
+      }
       lane.store(p, x_out, r_out, G_out, stats);
       p = (long long)atomicAdd(next, 1ull);
       has = p < hi;

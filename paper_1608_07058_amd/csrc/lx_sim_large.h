@@ -56,7 +56,7 @@ __device__ __forceinline__ double dg_large(int j, int k, const double* y) {
   return gj;
 }
 
-template <class P, class NET>
+template <class P, class NET, bool GRID = false>
 struct LaneL {
   typedef typename P::R R;
   static constexpr int N = NET::N;
@@ -76,6 +76,8 @@ struct LaneL {
   double t;
   u32 e;
   int status;
+  double tend;  // end of the current stretch: the next observation time (GRID)
+  int kt;       // index of that time (GRID)
   R a[M];
   R a0, a0c;
   u32 critw[W], ncrw[W], eqw[W];  // reaction sets, bit j % 32 of word j / 32
@@ -85,8 +87,14 @@ struct LaneL {
   u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip;
   long long n_nit;
 
+  // The time the trajectory runs to now: t_end, or the next observation time.
+  __device__ __forceinline__ double t_end_(const SimParams& prm) const {
+    if constexpr (GRID) return tend;
+    else return prm.t_end;
+  }
+
   __device__ __forceinline__ bool active(const SimParams& prm) const {
-    return status == LANE_OK && t < prm.t_end;
+    return status == LANE_OK && t < t_end_(prm);
   }
 
   __device__ static __forceinline__ bool bit(const u32* w, int j) {
@@ -116,11 +124,41 @@ struct LaneL {
     }
     status = bad ? LANE_BAD_INPUT : LANE_OK;
     t = prm.t_start;
+    if constexpr (GRID) {
+      kt = 0;
+      tend = prm.times[0];
+      if (!(tend >= t) || tend == LX_INF_F64) status = LANE_BAD_INPUT;
+    }
     e = 0;
     plan = false;
     implicit = false;
     ssa_left = 0;
     n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = 0;
+  }
+
+  // Observation times, as Lane::grid_next: record the state as row kt of
+  // x_grid (-1 if the time was not reached in status OK) and open the
+  // stretch to the next time; returns true if the trajectory goes on.
+  __device__ __forceinline__ bool grid_next(long long p, const SimParams& prm) {
+    const bool ok = status == LANE_OK;
+    int* row = prm.x_grid + ((long long)p * prm.n_times + kt) * N;
+    for (int i = 0; i < N; ++i) row[i] = ok ? x[i] : -1;
+    kt += 1;
+    if (ok && kt < prm.n_times) {
+      const double tn = prm.times[kt];
+      if ((tn >= t) & (tn != LX_INF_F64)) {
+        tend = tn;
+        ssa_left = 0;
+        plan = false;
+        return true;
+      }
+      status = LANE_BAD_INPUT;
+    }
+    for (int k = kt; k < prm.n_times; ++k) {
+      row += N;
+      for (int i = 0; i < N; ++i) row[i] = -1;
+    }
+    return false;
   }
 
   __device__ __forceinline__ void store(long long p, int* x_out, int* r_out, double* G_out,
@@ -252,9 +290,9 @@ struct LaneL {
   }
 
   __device__ __forceinline__ void absorb(const SimParams& prm) {
-    const double rem = prm.t_end - t;
+    const double rem = t_end_(prm) - t;
     for (int j = 0; j < M; ++j) G[j] = G[j] + g_large<NET>(j, x) * rem;
-    t = prm.t_end;
+    t = t_end_(prm);
   }
 
   // One SSA step (Gillespie 1977 direct method) with exact G.
@@ -266,7 +304,7 @@ struct LaneL {
     n_ssa += 1;
     const R E = -P::ulog(u1);
     const double tau_s = (double)(E / a0);
-    const double rem = prm.t_end - t;
+    const double rem = t_end_(prm) - t;
     if (tau_s >= rem) {
       absorb(prm);
       return;
@@ -358,7 +396,18 @@ struct LaneL {
           s[NET::NJ_SP[q]] = s[NET::NJ_SP[q]] + (double)NET::NJ_V[q] * ay;
         for (int qk = NET::RX_PTR[j]; qk < NET::RX_PTR[j + 1]; ++qk) {
           const int kk = NET::RX_SP[qk];
-          const double d = th[j] * dg_large<NET>(j, kk, y);
+          double d;
+          if (LXP(prm, jacobian)) {  // forward difference, as Lane::implicit_counts
+            const double yk = y[kk];
+            double yh;
+            const double hk = fd_step(yk, &yh);
+            y[kk] = yh;
+            const double ayh = th[j] * g_large_y<NET>(j, y);
+            y[kk] = yk;
+            d = (ayh - ay) / hk;
+          } else {
+            d = th[j] * dg_large<NET>(j, kk, y);
+          }
           for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q) {
             const int i = NET::NJ_SP[q];
             A[i * N + kk] = A[i * N + kk] + (double)NET::NJ_V[q] * d;
@@ -439,7 +488,7 @@ struct LaneL {
       if (jc < 0) jc = jlast;
     }
     double tau = (double)tau_r;
-    const double rem = prm.t_end - t;
+    const double rem = t_end_(prm) - t;
     bool last = false;
     if (tau >= rem) {
       tau = rem;
@@ -498,7 +547,7 @@ struct LaneL {
       r[j] = r[j] + k[j];
     }
     for (int i = 0; i < N; ++i) x[i] = xn[i];
-    t = last ? prm.t_end : t + tau;
+    t = last ? t_end_(prm) : t + tau;
     if (implicit) n_im += 1;
     else n_ex += 1;
     plan = false;
@@ -570,7 +619,7 @@ __device__ __forceinline__ void run_large(long long blk, const double* __restric
   long long p = lo + (long long)wave * prm.lanes + lane_id;
   bool has = lane_id < prm.lanes && p < hi;
   __shared__ int xlds[NET::N * LX_BLOCK];
-  LaneL<LX_POLICY, NET> lane;
+  LaneL<LX_POLICY, NET, LX_GRID_ON> lane;
   lane.x.p = xlds + threadIdx.x;
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
   while (has) {
@@ -579,6 +628,9 @@ __device__ __forceinline__ void run_large(long long blk, const double* __restric
       if (lane.active(prm) && !lane.in_ssa(prm)) lane.step(prm, key);
     }
     if (!lane.active(prm)) {
+      if constexpr (LX_GRID_ON) {
+        if (lane.grid_next(p, prm)) continue;
+      }
       lane.store(p, x_out, r_out, G_out, stats);
       p = (long long)atomicAdd(next, 1ull);
       has = p < hi;

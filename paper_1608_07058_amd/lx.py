@@ -28,7 +28,7 @@ EXPORTS = (
     "lx_test_uniform_f64", "lx_test_uniform_f32", "lx_test_math", "lx_test_poisson",
     "lx_test_exponential", "lx_test_tau_select", "lx_test_implicit", "lx_simulate_set",
     "lx_pf_workspace_size", "lx_pf_run", "lx_pf_graph_create", "lx_pf_graph_launch",
-    "lx_pf_graph_destroy", "lx_test_gamma",
+    "lx_pf_graph_destroy", "lx_test_gamma", "lx_simulate_grid",
 )
 
 
@@ -63,7 +63,8 @@ class Options(C.Structure):
         ("n_ssa_ex", C.c_int32), ("n_ssa_im", C.c_int32), ("lambda_thr", C.c_double),
         ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("block_size", C.c_int32),
         ("max_steps", C.c_int64), ("lanes_per_wave", C.c_int32), ("ssa_k", C.c_int32),
-        ("blocks_per_cu", C.c_int32), ("pid_stride", C.c_uint32), ("regroup", C.c_int32), ("lanes_per_traj", C.c_int32), ("reserved", C.c_int32 * 4),
+        ("blocks_per_cu", C.c_int32), ("pid_stride", C.c_uint32), ("regroup", C.c_int32), ("lanes_per_traj", C.c_int32), ("jacobian", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
 
@@ -79,11 +80,17 @@ _lib = None
 
 
 def lib():
-    """Load liblx.so (raises if it has not been built)."""
+    """Load liblx.so (raises if it has not been built).
+
+    torch is imported first: its HIP runtime is then the one liblx binds to,
+    so that device memory and streams of torch tensors and the library's
+    kernels belong to one runtime (loading liblx first would bring in a
+    second copy of the runtime next to torch's)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise LxError(f"{LIB_PATH} is missing: build it with paper_1608_07058_amd/build.py")
+        import torch  # noqa: F401  (see above)
         L = C.CDLL(LIB_PATH)
         P, I32, I64, U32, U64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
         L.lx_options_default.argtypes = [C.POINTER(Options)]
@@ -94,6 +101,8 @@ def lib():
         L.lx_network_destroy.argtypes = [P]
         L.lx_network_info.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
         L.lx_simulate.argtypes = [P, I64, P, P, D, D, I32, C.POINTER(Options), P, P, P, P, P]
+        L.lx_simulate_grid.argtypes = [P, I64, P, P, I32, P, D, I32, C.POINTER(Options), P, P, P,
+                                       P, P, P]
         L.lx_simulate_set.argtypes = [I32, C.POINTER(SetItem), D, D, I32, C.POINTER(Options), P]
         L.lx_pf_workspace_size.argtypes = [I64, I32, I32, C.POINTER(C.c_size_t)]
         L.lx_pf_run.argtypes = [C.POINTER(PfProblem), D, I32, C.POINTER(Options), P]
@@ -227,6 +236,44 @@ def simulate(net: Network, theta, x0, t_end: float, eps: float = 0.03, mode="ada
     _check(lib().lx_simulate(net.handle, P, th, xi, float(t_end), float(eps),
                              MODES.get(mode, mode), C.byref(o), xo, ro, go, so,
                              _stream_ptr(stream)), "lx_simulate")
+    return out
+
+
+def simulate_grid(net: Network, theta, x0, times, eps: float = 0.03, mode="adaptive", *,
+                  out=None, with_stats=True, stream=None, **opts):
+    """lx_simulate_grid on device tensors: ``simulate`` that also records the
+    state at each observation time.  ``times`` is a float64 [K] CUDA tensor
+    (non-decreasing, from t_start; the last one ends the simulation).  Returns
+    the dict of ``simulate`` plus ``x_grid`` int32 [P][K][N] (-1 in rows whose
+    time a trajectory did not reach with status OK).
+    """
+    import torch
+    P = theta.shape[0]
+    dev = theta.device
+    K = int(times.shape[0]) if times.dim() == 1 else -1
+    tt = _dev(times, torch.float64, (max(K, 0),), "times")
+    th = _dev(theta, torch.float64, (P, net.M), "theta")
+    xi = _dev(x0, torch.int32, (P, net.N), "x0")
+    out = dict(out or {})
+    if "x_grid" not in out:
+        out["x_grid"] = torch.empty((P, max(K, 0), net.N), dtype=torch.int32, device=dev)
+    if "x" not in out:
+        out["x"] = torch.empty((P, net.N), dtype=torch.int32, device=dev)
+    if "r" not in out:
+        out["r"] = torch.zeros((P, net.M), dtype=torch.int32, device=dev)
+    if "G" not in out:
+        out["G"] = torch.zeros((P, net.M), dtype=torch.float64, device=dev)
+    if with_stats and "stats" not in out:
+        out["stats"] = torch.empty((P, STATS_WORDS), dtype=torch.int64, device=dev)
+    xg = _dev(out["x_grid"], torch.int32, (P, max(K, 0), net.N), "x_grid")
+    xo = _dev(out["x"], torch.int32, (P, net.N), "x_out")
+    ro = _dev(out["r"], torch.int32, (P, net.M), "r_out")
+    go = _dev(out["G"], torch.float64, (P, net.M), "G_out")
+    so = _dev(out["stats"], torch.int64, (P, STATS_WORDS), "stats") if with_stats else None
+    o = options(**opts)
+    _check(lib().lx_simulate_grid(net.handle, P, th, xi, K, tt, float(eps), MODES.get(mode, mode),
+                                  C.byref(o), xg, xo, ro, go, so, _stream_ptr(stream)),
+           "lx_simulate_grid")
     return out
 
 

@@ -75,6 +75,16 @@ def dimer_stiff(scale=1000.0, x0=(10000, 0, 0)) -> Network:
     return _net("dimer_stiff", base.m, base.p, theta, x0, base.species, base.reactions)
 
 
+def dimer_rathinam(x0=(400, 798, 0)) -> Network:
+    """The stiff decaying-dimerizing set as Rathinam et al. (2003) pose it,
+    the third model of the paper's accuracy comparison: the same reactions as
+    ``dimer()`` with c = (1, 10, 1000, 0.1) and X0 = (400, 798, 0), where the
+    dimerization pair is near partial equilibrium from the start."""
+    base = dimer(x0)
+    return _net("dimer_rathinam", base.m, base.p, [1.0, 10.0, 1000.0, 0.1], x0, base.species,
+                base.reactions)
+
+
 def isomerisation(kf=1.0, kb=1.0, n_total=1000) -> Network:
     """A -> B (kf), B -> A (kb), all N_total molecules start as A."""
     return _net("isomerisation", [[1, 0], [0, 1]], [[0, 1], [1, 0]], [kf, kb], [n_total, 0],
@@ -227,6 +237,15 @@ def dimer_workload(P=16384) -> Workload:
     th, x0 = tile(net, P)
     return Workload("decaying-dimerizing X0=(10000,0,0) t_end=30", [net], P, 30.0, "adaptive",
                     theta=[th], x0=[x0], pid=[np.arange(P, dtype=np.int64)])
+
+
+def rathinam_workload(P=16384) -> Workload:
+    """The stiff decaying-dimerizing set of Rathinam et al. (2003), the
+    implicit-leap-heavy workload (timing the Jacobian variants)."""
+    net = dimer_rathinam()
+    th, x0 = tile(net, P)
+    return Workload("stiff decaying-dimerizing (Rathinam 2003) X0=(400,798,0) t_end=4", [net], P,
+                    4.0, "adaptive", theta=[th], x0=[x0], pid=[np.arange(P, dtype=np.int64)])
 
 
 def mixed_set_workload(P=1 << 20, seed=3) -> Workload:

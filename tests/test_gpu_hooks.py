@@ -154,8 +154,9 @@ def test_step_decision_bit_exact(lxm, orc, name, mode, precision):
     assert np.array_equal(got["action"], ref["action"])
 
 
+@pytest.mark.parametrize("jacobian", [0, 1])
 @pytest.mark.parametrize("name", ["dimer", "dimer_stiff", "isomerisation", "schlogl"])
-def test_implicit_solve_bit_exact(lxm, orc, name):
+def test_implicit_solve_bit_exact(lxm, orc, name, jacobian):
     net = NETS[name]
     rng = np.random.default_rng(21)
     Q = 1000
@@ -166,8 +167,8 @@ def test_implicit_solve_bit_exact(lxm, orc, name):
     Pj = rng.poisson(np.minimum(res["a"] * tau[:, None], 1e6))
     jc = np.where(rng.uniform(size=Q) < 0.3, rng.integers(0, net.M, Q), -1).astype(np.int32)
     h = lxm.Network(net.m, net.p)
-    got = lxm.test_implicit(h, th, x, tau, Pj, jc)
-    ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc)
+    got = lxm.test_implicit(h, th, x, tau, Pj, jc, jacobian=jacobian)
+    ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc, jacobian=jacobian)
     assert np.array_equal(got["ok"], ref["ok"])
     assert np.array_equal(got["iters"], ref["iters"])
     assert np.array_equal(got["k"], ref["k"])

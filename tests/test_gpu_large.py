@@ -83,17 +83,19 @@ def test_random_network_elementwise(lxm, orc, precision, schedule):
     assert got["stats"]["steps_explicit"].sum() > 0 and got["stats"]["steps_ssa"].sum() > 0
 
 
-@pytest.mark.parametrize("mode", ["adaptive", "explicit", "ssa"])
+@pytest.mark.parametrize("mode", ["adaptive", "explicit", "ssa", "adaptive-fd"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_stiff_padded_elementwise(lxm, orc, precision, mode):
+    jac = {"jacobian": 1} if mode == "adaptive-fd" else {}
+    mode = mode.replace("-fd", "")
     net = STIFF
     P = 200
     theta, x0 = W.tile(net, P)
     theta = theta * np.random.default_rng(7).gamma(4.0, 0.25, size=theta.shape)
     t_end = 0.05 if mode == "ssa" else 0.5
     got = _gpu(lxm, net, theta, x0, t_end, mode, precision=precision, schedule="batched",
-               lanes_per_wave=32, ssa_k=3)
-    ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode=mode, precision=precision)
+               lanes_per_wave=32, ssa_k=3, **jac)
+    ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode=mode, precision=precision, **jac)
     _same(got, ref, f"stiff/{precision}/{mode}")
     if mode == "adaptive":
         assert got["stats"]["steps_implicit"].sum() > 0
@@ -144,7 +146,8 @@ def test_step_decision_bit_exact(lxm, orc, name, precision):
         assert ref["eq"].any()
 
 
-def test_implicit_solve_48_bit_exact(lxm, orc):
+@pytest.mark.parametrize("jacobian", [0, 1])
+def test_implicit_solve_48_bit_exact(lxm, orc, jacobian):
     net = STIFF
     assert net.N == 48
     rng = np.random.default_rng(9)
@@ -155,8 +158,8 @@ def test_implicit_solve_48_bit_exact(lxm, orc):
     res = orc.tau_select(net.m, net.p, th, x)
     Pj = rng.poisson(np.minimum(res["a"] * tau[:, None], 1e6))
     jc = np.where(rng.uniform(size=Q) < 0.3, rng.integers(0, net.M, Q), -1).astype(np.int32)
-    got = lxm.test_implicit(_handle(lxm, net), th, x, tau, Pj, jc)
-    ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc)
+    got = lxm.test_implicit(_handle(lxm, net), th, x, tau, Pj, jc, jacobian=jacobian)
+    ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc, jacobian=jacobian)
     assert np.array_equal(got["ok"], ref["ok"])
     assert np.array_equal(got["iters"], ref["iters"])
     assert np.array_equal(got["k"], ref["k"])
@@ -177,3 +180,26 @@ def test_large_network_limits(lxm):
     for bad in (dict(lanes_per_traj=4), dict(regroup=2)):
         with pytest.raises(lxm.LxError):
             lxm.simulate(_handle(lxm, RANDOM), th, xi, 0.01, schedule="batched", **bad)
+
+
+@pytest.mark.parametrize("schedule", ["plain", "batched"])
+def test_observation_times_elementwise(lxm, orc, schedule):
+    # lx_simulate_grid on both large networks: states at every observation
+    # time, X, r, G and statistics identical to the oracle's
+    import torch
+    cases = ((RANDOM, *_random_inputs(150), np.array([0.02, 0.05, 0.05, 0.1]), "adaptive"),
+             (STIFF, *W.tile(STIFF, 100), np.array([0.0, 0.2, 0.4, 0.5]), "adaptive"))
+    for net, theta, x0, times, mode in cases:
+        print(f"large grid {net.name} {schedule}", flush=True)
+        res = lxm.simulate_grid(_handle(lxm, net), torch.as_tensor(theta, device="cuda"),
+                                torch.as_tensor(np.ascontiguousarray(x0, np.int32), device="cuda"),
+                                torch.as_tensor(times, device="cuda"), 0.03, mode,
+                                precision="mixed", schedule=schedule)
+        torch.cuda.synchronize()
+        got = {"x_grid": res["x_grid"].cpu().numpy(), "x": res["x"].cpu().numpy(),
+               "r": res["r"].cpu().numpy(), "G": res["G"].cpu().numpy(),
+               "stats": lxm.stats_numpy(res["stats"])}
+        ref = orc.simulate_grid(net.m, net.p, theta, x0, times, mode=mode, precision="mixed")
+        assert np.array_equal(got["x_grid"], ref["x_grid"]), net.name
+        _same(got, ref, f"{net.name} grid {schedule}")
+        assert np.all(got["stats"]["status"] == 0)

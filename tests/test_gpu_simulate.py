@@ -101,6 +101,26 @@ def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision, schedule
     assert np.all(got["stats"]["status"] == 0)
 
 
+@pytest.mark.parametrize("schedule", ["plain", "batched", "group4"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,t_end", [("dimer_stiff", 3.0), ("dimer_rathinam", 2.0),
+                                        ("isomerisation", 5.0)])
+def test_fd_jacobian_matches_oracle_elementwise(lxm, orc, name, t_end, precision, schedule):
+    # implicit leaps with the forward-difference Jacobian
+    net = getattr(W, name)()
+    P = 300
+    theta = W.gamma_prior_theta(net, P, seed=29)
+    _, x0 = W.tile(net, P)
+    kw = {"group4": dict(schedule="batched", lanes_per_traj=4)}.get(schedule, dict(schedule=schedule))
+    got = gpu_run(lxm, net, theta, x0, t_end, "adaptive", precision=precision, jacobian=1, **kw)
+    ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode="adaptive", precision=precision,
+                       jacobian=1)
+    assert_same(got, ref, f"{name}/{precision}/{schedule}/fd")
+    assert got["stats"]["steps_implicit"].sum() > 0
+    with pytest.raises(lxm.LxError):
+        gpu_run(lxm, net, theta[:2], x0[:2], t_end, "adaptive", jacobian=2)
+
+
 @pytest.mark.parametrize("knobs", [
     dict(lanes_per_wave=4, ssa_k=2, blocks_per_cu=1),
     dict(lanes_per_wave=8, ssa_k=8, blocks_per_cu=2, block_size=64),
