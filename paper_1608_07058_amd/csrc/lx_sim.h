@@ -81,9 +81,41 @@ __device__ __forceinline__ double dg_of(int j, int k, const double (&y)[NET::N])
 }
 
 // Cross-lane read within groups of TPL lanes (lane s of the caller's group).
+// Groups of 2 and 4 lanes lie within a quad of the wave, so the read is a
+// DPP quad permutation (a VALU move, no LDS round trip); `s` is a
+// compile-time constant after unrolling, so the switch folds to one case.
+template <int TPL>
+__device__ __forceinline__ int group_read_b32(int v, int s) {
+  if constexpr (TPL == 4) {
+    switch (s) {
+      case 0: return __builtin_amdgcn_update_dpp(0, v, 0x00, 0xF, 0xF, false);
+      case 1: return __builtin_amdgcn_update_dpp(0, v, 0x55, 0xF, 0xF, false);
+      case 2: return __builtin_amdgcn_update_dpp(0, v, 0xAA, 0xF, 0xF, false);
+      default: return __builtin_amdgcn_update_dpp(0, v, 0xFF, 0xF, 0xF, false);
+    }
+  } else if constexpr (TPL == 2) {
+    if (s == 0) return __builtin_amdgcn_update_dpp(0, v, 0xA0, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, 0xF5, 0xF, 0xF, false);
+  } else {
+    return __shfl(v, s, TPL);
+  }
+}
+
 template <int TPL, class T>
 __device__ __forceinline__ T group_read(T v, int s) {
-  return __shfl(v, s, TPL);
+  if constexpr (TPL == 2 || TPL == 4) {
+    if constexpr (sizeof(T) == 4) {
+      return __builtin_bit_cast(T, group_read_b32<TPL>(__builtin_bit_cast(int, v), s));
+    } else {
+      static_assert(sizeof(T) == 8, "32- or 64-bit values");
+      const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+      const unsigned lo = (unsigned)group_read_b32<TPL>((int)(unsigned)b, s);
+      const unsigned hi = (unsigned)group_read_b32<TPL>((int)(unsigned)(b >> 32), s);
+      return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    }
+  } else {
+    return __shfl(v, s, TPL);
+  }
 }
 
 // Lane state of one trajectory.  With TPL > 1 a trajectory occupies TPL lanes
