@@ -225,9 +225,14 @@ def bench_set(args, torch, lx, W):
     xx = [torch.as_tensor(x, device="cuda") for x in wl.x0]
     outs = [None] * len(hs)
     results = {}
+    from paper_1608_07058_amd import autotune
     for form in [f for f in args.forms.split(",") if f.startswith("batched")]:
         opts = dict(FORMS[form])
         opts.pop("schedule")
+        if not args.untuned:
+            # knobs found by paper_1608_07058_amd/autotune.py for this set, if any
+            opts.update(autotune.lookup_set([(n.m, n.p) for n in wl.nets], wl.P,
+                                            opts["precision"], wl.mode))
         if args.options:
             opts.update(json.loads(args.options))
         stream = torch.cuda.current_stream()

@@ -243,9 +243,11 @@ typedef struct lx_set_item {
 } lx_set_item;
 
 /* Simulate several networks in one launch (batched schedule): K in [1, 8]
- * items, each with its own network, ensemble and buffers; blocks are assigned
- * to items in proportion to their sizes, each block runs one network, so no
- * wave mixes networks.  Results are identical to K separate lx_simulate calls
+ * items, each with its own network, ensemble and buffers.  Every block owns
+ * an equal slice of every item and runs the items one after another (a wave
+ * moves to the next item as soon as its lanes have drained the block's slice
+ * of the current one), so networks of very different cost still load every
+ * block alike and no wave mixes networks at a time.  Results are identical to K separate lx_simulate calls
  * with the same ids.  t_end, eps, mode and options (precision, control
  * constants, seed, rng_stream, accumulate, tuning) are shared; opt->schedule,
  * pid_base and pid_stride are ignored in favour of the items.  Errors as for
@@ -347,7 +349,9 @@ lx_status lx_test_tau_select(lx_network net, int64_t Q, const double* theta, con
                              void* stream);
 /* Implicit-leap solve for Q cases: given tau [Q], Poisson draws Pj [Q][M]
  * (int64) and critical firing jc [Q] (-1 none), the non-critical set
- * {j : a_j > 0, j != jc}; outputs k [Q][M] (int64), ok [Q], iters [Q]. */
+ * {j : a_j > 0, j != jc}; outputs k [Q][M] (int64), ok [Q], iters [Q].
+ * opt->jacobian selects the analytic or forward-difference Jacobian;
+ * newton_tol and newton_maxit apply. */
 lx_status lx_test_implicit(lx_network net, int64_t Q, const double* theta, const int32_t* x,
                            const double* tau, const int64_t* Pj, const int32_t* jc,
                            const lx_options* opt, int64_t* k, int32_t* ok, int32_t* iters,

@@ -96,6 +96,66 @@ def tune(lx, h, theta, x0, t_end, eps, mode, precision, grid=None, reps=2, log=N
     return best[0], table
 
 
+# Knobs swept for a network set (lx_simulate_set): one lane per trajectory,
+# the set's blocks sized by the scheduler.
+SET_GRID = {
+    "lanes_per_wave": (64,),
+    "ssa_k": (4, 8, 16),
+    "block_size": (128, 256),
+    "blocks_per_cu": (2, 4, 6, 8),
+}
+
+
+def key_of_set(nets, P, precision, mode, arch="gfx950"):
+    import numpy as np
+    h = hashlib.sha1()
+    for m, p in nets:
+        h.update(np.ascontiguousarray(m, np.int32).tobytes())
+        h.update(np.ascontiguousarray(p, np.int32).tobytes())
+    return f"{arch}/set-{h.hexdigest()[:16]}/P{P}/{precision}/{mode}"
+
+
+def lookup_set(nets, P, precision, mode, path=DEFAULT_FILE):
+    """Tuned options for a network set ([(m, p), ...], P trajectories in
+    total), or {} if it was never tuned."""
+    return dict(load(path).get(key_of_set(nets, P, precision, mode), {}).get("options", {}))
+
+
+def tune_set(lx, items, t_end, eps, mode, precision, grid=None, reps=1, log=None):
+    """tune() for lx_simulate_set: ``items`` as for lx.simulate_set."""
+    import torch
+    grid = grid or SET_GRID
+    stream = torch.cuda.current_stream()
+    names = list(grid)
+    table = []
+    outs = [None] * len(items)
+
+    def run(kw):
+        res = lx.simulate_set([dict(it, out=outs[k]) for k, it in enumerate(items)], t_end, eps,
+                              mode, stream=stream, **kw)
+        for k in range(len(items)):
+            outs[k] = res[k]
+
+    for values in itertools.product(*(grid[n] for n in names)):
+        opts = dict(zip(names, values))
+        kw = dict(precision=precision, **opts)
+        run(kw)  # warm-up
+        times = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            run(kw)
+            b.record(stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = min(times)
+        table.append((opts, ms))
+        if log:
+            log(f"[tune] {opts} {ms:.3f} ms")
+    best = min(table, key=lambda t: t[1])
+    return best[0], table
+
+
 def save(key, options, ms, table, path=DEFAULT_FILE):
     data = load(path)
     data[key] = {"options": options, "ms": ms,
@@ -106,13 +166,16 @@ def save(key, options, ms, table, path=DEFAULT_FILE):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--workload", default="dimer", choices=("dimer", "birth_death", "telegraph"))
+    ap.add_argument("--workload", default="dimer",
+                    choices=("dimer", "birth_death", "telegraph", "mixed_set"))
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--out", default=DEFAULT_FILE)
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     import torch
     from paper_1608_07058_amd import lx, workloads as W
+    if args.workload == "mixed_set":
+        return main_set(args, torch, lx, W)
     wl = {"dimer": W.dimer_workload, "birth_death": W.birth_death_workload,
           "telegraph": W.telegraph_workload}[args.workload]()
     net = wl.nets[0]
@@ -123,6 +186,22 @@ def main():
                        log=lambda s: print(s, flush=True))
     ms = min(t for _, t in table)
     key = key_of(net.m, net.p, wl.P, args.precision, wl.mode)
+    save(key, best, ms, table, args.out)
+    print(json.dumps({"key": key, "best": best, "ms": ms}), flush=True)
+
+
+def main_set(args, torch, lx, W):
+    """Tune the three-network set of the mixed-set workload (particle p runs
+    network p mod 3)."""
+    wl = W.mixed_set_workload()
+    hs = [lx.Network(n.m, n.p) for n in wl.nets]
+    items = [{"net": h, "theta": torch.as_tensor(t, device="cuda"),
+              "x0": torch.as_tensor(x, device="cuda"), "pid_base": k, "pid_stride": len(hs)}
+             for k, (h, t, x) in enumerate(zip(hs, wl.theta, wl.x0))]
+    best, table = tune_set(lx, items, wl.t_end, wl.eps, wl.mode, args.precision,
+                           log=lambda s: print(s, flush=True))
+    ms = min(t for _, t in table)
+    key = key_of_set([(n.m, n.p) for n in wl.nets], wl.P, args.precision, wl.mode)
     save(key, best, ms, table, args.out)
     print(json.dumps({"key": key, "best": best, "ms": ms}), flush=True)
 

@@ -305,7 +305,10 @@ std::string kernel_source(const lx_network_s& net, const char* variant, int prec
 }
 
 // hipRTC source of the multi-network kernel: every network of the set as
-// LxNet<k>, and a kernel that picks the network of its block.
+// LxNet<k>.  Every block owns a slice of every network and runs the
+// networks one after another (each wave moves on as soon as its lanes have
+// drained the block's slice), so that all blocks carry the same mix of work
+// whatever the networks' costs.
 std::string set_source(const std::vector<const lx_network_s*>& nets, int precision, int block,
                        int tpl, const std::string& consts) {
   std::ostringstream src;
@@ -318,19 +321,24 @@ std::string set_source(const std::vector<const lx_network_s*>& nets, int precisi
   src << "typedef LxNet0 LxNet;\n" << lx_src_sim << "\n";
   src << "extern \"C\" __global__ void __launch_bounds__(LX_BLOCK)\n"
          "    lx_sim_set(lx::SetArgs a, lx::SimParams prm) {\n"
-         "  __shared__ unsigned long long next;\n"
-         "  int k = 0;\n"
-         "  while (k + 1 < a.K && (int)blockIdx.x >= a.it[k + 1].block_begin) ++k;\n"
-         "  const lx::SetItem& it = a.it[k];\n"
-         "  lx::SimParams q = prm;\n"
-         "  q.P = it.P;\n  q.per_block = it.per_block;\n  q.lanes = it.lanes;\n"
-         "  q.pid_base = it.pid_base;\n  q.pid_stride = it.pid_stride;\n"
-         "  const long long blk = (long long)blockIdx.x - it.block_begin;\n"
-         "  switch (k) {\n";
+         "  __shared__ unsigned long long next[" << nets.size() << "];\n"
+         "  const long long blk = blockIdx.x;\n"
+         "  const long long waves = blockDim.x >> 6;\n"
+         "  if (threadIdx.x == 0) {\n";
   for (size_t k = 0; k < nets.size(); ++k)
-    src << "    case " << k << ": lx::run_sched<LxNet" << k
-        << ">(blk, it.theta, it.x0, it.x_out, it.r_out, it.G_out, it.stats, q, &next); break;\n";
-  src << "  }\n}\n";
+    src << "    next[" << k << "] = (unsigned long long)(blk * a.it[" << k << "].per_block + waves * a.it["
+        << k << "].lanes);\n";
+  src << "  }\n  __syncthreads();\n";
+  for (size_t k = 0; k < nets.size(); ++k)
+    src << "  {\n    const lx::SetItem& it = a.it[" << k << "];\n"
+        << "    lx::SimParams q = prm;\n"
+        << "    q.P = it.P;\n    q.per_block = it.per_block;\n    q.lanes = it.lanes;\n"
+        << "    q.pid_base = it.pid_base;\n    q.pid_stride = it.pid_stride;\n"
+        << "    if (blk * it.per_block < it.P)\n"
+        << "      lx::run_sched<LxNet" << k
+        << ">(blk, it.theta, it.x0, it.x_out, it.r_out, it.G_out, it.stats, q, &next[" << k
+        << "], true);\n  }\n";
+  src << "}\n";
   return src.str();
 }
 
@@ -796,13 +804,13 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
   if (st != LX_OK) return st;
   const int lanes = traj_per_wave(o, total, cus);
   const long long round = (long long)(block / 64) * lanes;
-  const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
-  long long per_block = (total + max_grid - 1) / max_grid;
-  if (per_block < round) per_block = round;
+  // resident blocks, but no more than give every block a full round of lanes
+  long long grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
+  const long long fill = (total + round - 1) / round;
+  if (grid > fill) grid = fill;
   lx::SetArgs args;
   memset(&args, 0, sizeof(args));
   args.K = K;
-  long long begin = 0;
   std::vector<const lx_network_s*> nets;
   std::ostringstream key;
   key << "set/" << o.precision << "/" << block << "/tpl" << tpl_of(o);
@@ -816,17 +824,13 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
     d.G_out = it.G_out;
     d.stats = (lx::Stats*)it.stats;
     d.P = it.P;
-    d.per_block = per_block;
+    d.per_block = (it.P + grid - 1) / grid;
     d.lanes = lanes;
     d.pid_base = it.pid_base;
     d.pid_stride = it.pid_stride ? it.pid_stride : 1;
-    d.block_begin = (int)begin;
-    d.blocks = (int)((it.P + per_block - 1) / per_block);
-    begin += d.blocks;
     nets.push_back(it.net);
     key << "/" << std::hex << fnv1a(it.net->netsrc) << std::dec;
   }
-  if (begin > 0x7fffffffLL) return fail(LX_E_INVALID, "ensemble too large for one launch");
   finish_params(o, true, &prm);
   const std::string consts = const_source(prm);
   key << "/c" << std::hex << fnv1a(consts) << std::dec;
@@ -836,7 +840,7 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
                       "lx_sim_set", &fn);
   if (st != LX_OK) return st;
   void* kargs[] = {(void*)&args, (void*)&prm};
-  hipError_t e = hipModuleLaunchKernel(fn, (unsigned)begin, 1, 1, (unsigned)block, 1, 1, 0,
+  hipError_t e = hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0,
                                        (hipStream_t)stream, kargs, nullptr);
   if (e != hipSuccess) return hip_fail(e, "launch lx_sim_set");
   return LX_OK;

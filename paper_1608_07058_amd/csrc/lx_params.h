@@ -55,7 +55,8 @@ struct Stats {
       kclip, attempts;
 };
 
-// One network of a multi-network launch (lx_simulate_set).
+// One network of a multi-network launch (lx_simulate_set): every block of
+// the launch owns the slice [blk * per_block, (blk + 1) * per_block) of it.
 struct SetItem {
   const double* theta;
   const int* x0;
@@ -64,7 +65,7 @@ struct SetItem {
   double* G_out;
   Stats* stats;
   long long P, per_block;
-  int block_begin, blocks, lanes, pad;
+  int lanes, pad;
   unsigned int pid_base, pid_stride;
 };
 

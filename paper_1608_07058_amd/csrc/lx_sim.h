@@ -1001,7 +1001,7 @@ template <class NET>
 __device__ __forceinline__ void run_batched(long long blk, const double* __restrict__ theta,
                                             const int* __restrict__ x0, int* x_out, int* r_out,
                                             double* G_out, Stats* stats, const SimParams& prm,
-                                            unsigned long long* next) {
+                                            unsigned long long* next, bool cursor_ready) {
   constexpr int TPL = LX_TPL;
   const int lane_id = threadIdx.x & 63;
   const int slot = lane_id / TPL;  // trajectory slot of this lane in its wave
@@ -1011,8 +1011,10 @@ __device__ __forceinline__ void run_batched(long long blk, const double* __restr
   const long long lo = blk * prm.per_block;
   long long hi = lo + prm.per_block;
   if (hi > prm.P) hi = prm.P;
-  if (threadIdx.x == 0) *next = (unsigned long long)(lo + (long long)waves * prm.lanes);
-  __syncthreads();
+  if (!cursor_ready) {
+    if (threadIdx.x == 0) *next = (unsigned long long)(lo + (long long)waves * prm.lanes);
+    __syncthreads();
+  }
   const Key key{prm.k0, prm.k1};
   long long p = lo + (long long)wave * prm.lanes + slot;
   bool has = slot < prm.lanes && p < hi;
@@ -1050,7 +1052,7 @@ template <class NET>
 __device__ __forceinline__ void run_regroup(long long blk, const double* __restrict__ theta,
                                             const int* __restrict__ x0, int* x_out, int* r_out,
                                             double* G_out, Stats* stats, const SimParams& prm,
-                                            unsigned long long* next) {
+                                            unsigned long long* next, bool cursor_ready) {
   typedef Lane<LX_POLICY, NET, 1, LX_GRID_ON> LaneT;
   constexpr int STRIDE = LaneT::STATE_WORDS;
   __shared__ u32 slots[LX_BLOCK * STRIDE];
@@ -1063,8 +1065,10 @@ __device__ __forceinline__ void run_regroup(long long blk, const double* __restr
   const long long lo = blk * prm.per_block;
   long long hi = lo + prm.per_block;
   if (hi > prm.P) hi = prm.P;
-  if (threadIdx.x == 0) *next = (unsigned long long)(lo + (long long)waves * prm.lanes);
-  __syncthreads();
+  if (!cursor_ready) {
+    if (threadIdx.x == 0) *next = (unsigned long long)(lo + (long long)waves * prm.lanes);
+    __syncthreads();
+  }
   const Key key{prm.k0, prm.k1};
   long long p = lo + vslot;
   bool has = slot_thread && p < hi;
@@ -1121,14 +1125,17 @@ __device__ __forceinline__ void run_regroup(long long blk, const double* __restr
   }
 }
 
+// `cursor_ready`: the caller has set *next to the first particle after the
+// block's initial lanes and synchronised the block (network sets set every
+// network's cursor at once and run the networks back to back).
 template <class NET>
 __device__ __forceinline__ void run_sched(long long blk, const double* __restrict__ theta,
                                           const int* __restrict__ x0, int* x_out, int* r_out,
                                           double* G_out, Stats* stats, const SimParams& prm,
-                                          unsigned long long* next) {
+                                          unsigned long long* next, bool cursor_ready = false) {
   if (LX_TPL == 1 && LXP(prm, regroup) > 0)
-    run_regroup<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next);
-  else run_batched<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next);
+    run_regroup<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next, cursor_ready);
+  else run_batched<NET>(blk, theta, x0, x_out, r_out, G_out, stats, prm, next, cursor_ready);
 }
 }  // namespace lx
 #endif

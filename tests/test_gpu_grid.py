@@ -211,3 +211,31 @@ def test_grid_full_size_dimer_sampled(lxm, orc):
         for k in ("x_grid", "x", "r", "G"):
             assert np.array_equal(got[k][p], one[k][0]), (int(p), k)
         assert got["stats"]["attempts"][p] == one["stats"]["attempts"][0]
+
+
+def test_grid_split_run_with_accumulation(lxm, orc):
+    # the second half of a run: t_start 10, r and G carried in (accumulate),
+    # observation times from t_start on; another random stream
+    import torch
+    net = W.telegraph()
+    P = 1500
+    theta = W.gamma_prior_theta(net, P, seed=31)
+    _, x0 = W.tile(net, P)
+    first = orc.simulate(net.m, net.p, theta, x0, 10.0, mode="adaptive", precision="mixed")
+    times = np.array([10.0, 12.5, 15.0, 20.0])
+    ref = orc.simulate_grid(net.m, net.p, theta, first["x"], times, mode="adaptive",
+                            precision="mixed", t_start=10.0, rng_stream=1, r0=first["r"],
+                            G0=first["G"])
+    for sched in (dict(schedule="plain"), dict(schedule="batched", lanes_per_traj=4)):
+        out = {"r": torch.as_tensor(first["r"], device="cuda"),
+               "G": torch.as_tensor(first["G"], device="cuda")}
+        res = lxm.simulate_grid(_handle(lxm, net), torch.as_tensor(theta, device="cuda"),
+                                torch.as_tensor(first["x"], device="cuda"),
+                                torch.as_tensor(times, device="cuda"), out=out, precision="mixed",
+                                t_start=10.0, rng_stream=1, accumulate=1, **sched)
+        torch.cuda.synchronize()
+        got = {"x_grid": res["x_grid"].cpu().numpy(), "x": res["x"].cpu().numpy(),
+               "r": res["r"].cpu().numpy(), "G": res["G"].cpu().numpy(),
+               "stats": lxm.stats_numpy(res["stats"])}
+        assert_same(got, ref, f"split {sched}")
+        assert np.array_equal(got["x_grid"][:, 0], first["x"])

@@ -406,6 +406,32 @@ def test_set_matches_oracle(lxm, orc, precision):
         assert_same(alone, ref, f"{net.name} alone")
 
 
+@pytest.mark.parametrize("knobs", [dict(), dict(blocks_per_cu=8, ssa_k=8),
+                                   dict(regroup=2, lanes_per_wave=32, block_size=128),
+                                   dict(lanes_per_traj=4, blocks_per_cu=1)])
+def test_set_uneven_sizes(lxm, orc, knobs):
+    # items of 0, 5 and 7001 trajectories: every block owns a slice of each
+    # network, most blocks none of the small ones
+    import torch
+    nets = [W.birth_death(), W.schlogl(), W.telegraph()]
+    sizes = [0, 5, 7001]
+    items, refs = [], []
+    for k, (net, P) in enumerate(zip(nets, sizes)):
+        th = W.gamma_prior_theta(net, P, seed=40 + k)
+        _, x0 = W.tile(net, P)
+        items.append(dict(net=_handle(lxm, net), theta=torch.as_tensor(th, device="cuda"),
+                          x0=torch.as_tensor(x0, device="cuda"), pid_base=1000 * k))
+        refs.append(orc.simulate(net.m, net.p, th, x0, 20.0, mode="adaptive", precision="mixed",
+                                 pid_base=1000 * k) if P else None)
+    outs = lxm.simulate_set(items, 20.0, 0.03, "adaptive", precision="mixed", **knobs)
+    torch.cuda.synchronize()
+    assert outs[0]["x"].shape[0] == 0
+    for k in (1, 2):
+        got = {"x": outs[k]["x"].cpu().numpy(), "r": outs[k]["r"].cpu().numpy(),
+               "G": outs[k]["G"].cpu().numpy(), "stats": lxm.stats_numpy(outs[k]["stats"])}
+        assert_same(got, refs[k], f"{nets[k].name} {knobs}")
+
+
 def test_set_full_size_sampled(lxm, orc):
     # The 2^20-particle mixed ensemble in one launch, checked on sampled
     # particles of each network recomputed by the oracle.
