@@ -172,6 +172,11 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
         "events_per_s": r_total / (ms / 1e3),
         "events_per_trajectory": r_total / wl.P,
         "attempts_per_trajectory": float(stats["attempts"].mean()),
+        "steps_per_trajectory": {m: float(stats["steps_" + m].mean())
+                                 for m in ("ssa", "explicit", "implicit")},
+        "steps_per_s": {m: float(stats["steps_" + m].sum()) / (ms / 1e3)
+                        for m in ("ssa", "explicit", "implicit")},
+        "rejections_per_trajectory": float(stats["rejections"].mean()),
         "lane_status_ok": bool((stats["status"] == 0).all()),
         "precision": opts["precision"],
         "schedule": opts["schedule"],
@@ -422,7 +427,8 @@ def main():
         what = (f"all {wl.P} trajectories of the workload" if n_cpu == wl.P else
                 f"the first {n_cpu} of the {wl.P} trajectories")
         cpu = {"value": n_cpu / dt, "unit": "trajectories/s", "cores": nth, "kind": "oracle",
-               "sample": f"{what}, fp64 oracle, {nth} threads, {dt:.1f} s"}
+               "sample": f"{what}, fp64 oracle, {nth} threads, {dt:.1f} s",
+               "per_core": n_cpu / dt / nth}
         log(args, f"[bench] oracle: {cpu}")
     roof = None
     if ops_per_traj is not None:

@@ -44,6 +44,9 @@ typedef int32_t lx_status;
 #define LX_E_HIP (-3)         /* HIP runtime error (launch, module load) */
 #define LX_E_UNSUPPORTED (-4) /* device is not gfx950, or network too large */
 #define LX_E_NOMEM (-5)       /* host or device allocation failed */
+/* Warning (positive): the simulation ran, and some trajectories ended with a
+ * status other than LX_LANE_OK (only with lx_options.check_lanes set). */
+#define LX_W_LANE_FAIL 1
 
 /* Simulation modes (paper, Results section: adaptive by default, or fully
  * explicit tau-leaping, or SSA only). */
@@ -120,7 +123,13 @@ typedef struct lx_options {
                            Jacobian gives) or LX_JAC_FD (1, forward differences with the
                            step 2^-26 max(|y_k|, 1): the numerically estimated Jacobian
                            (Background section) */
-  int32_t reserved[3];
+  int32_t check_lanes;  /* 1: after launching, wait for the stream and read the status
+                           of every trajectory from `stats` (which must then be
+                           given); return LX_W_LANE_FAIL if any is not LX_LANE_OK,
+                           with the count and the first one in lx_last_error().
+                           The call is then synchronous.  0 (default): return at
+                           once; statuses are in `stats` when the stream is done */
+  int32_t reserved[2];
 } lx_options;
 
 /* Per-trajectory statistics (80 bytes). */

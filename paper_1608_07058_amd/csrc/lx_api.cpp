@@ -498,6 +498,34 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
   return LX_OK;
 }
 
+// With opt.check_lanes: wait for the stream, read the status word of every
+// record of `stats` (strided copy of 4 bytes out of each lx_stats), and
+// report trajectories that ended with a status other than LANE_OK.
+lx_status check_lanes(const lx_options& o, int64_t P, const lx_stats* stats, hipStream_t s,
+                      int64_t* failed) {
+  *failed = 0;
+  if (!o.check_lanes || P == 0) return LX_OK;
+  if (!stats) return fail(LX_E_INVALID, "check_lanes needs the stats buffer");
+  std::vector<int32_t> st((size_t)P);
+  hipError_t e = hipMemcpy2DAsync(st.data(), sizeof(int32_t), stats, sizeof(lx_stats),
+                                  sizeof(int32_t), (size_t)P, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "reading lane statuses");
+  int64_t first = -1;
+  for (int64_t p = 0; p < P; ++p)
+    if (st[(size_t)p] != 0) {
+      if (first < 0) first = p;
+      *failed += 1;
+    }
+  if (*failed) {
+    std::ostringstream m;
+    m << *failed << " of " << P << " trajectories ended with a non-OK status (first: row "
+      << first << ", status " << st[(size_t)first] << ")";
+    g_err = m.str();
+  }
+  return LX_OK;
+}
+
 // A resolved simulation launch: kernel, geometry and parameters.
 struct SimLaunch {
   hipFunction_t fn = nullptr;
@@ -740,7 +768,12 @@ lx_status lx_simulate(lx_network net, int64_t P, const double* theta, const int3
   SimLaunch L;
   st = plan_sim(net, P, o, t_end, eps, mode, &L);
   if (st != LX_OK) return st;
-  return launch_sim(L, L.prm, theta, x0, x_out, r_out, G_out, stats, (hipStream_t)stream);
+  st = launch_sim(L, L.prm, theta, x0, x_out, r_out, G_out, stats, (hipStream_t)stream);
+  if (st != LX_OK) return st;
+  int64_t failed = 0;
+  st = check_lanes(o, P, stats, (hipStream_t)stream, &failed);
+  if (st != LX_OK) return st;
+  return failed ? LX_W_LANE_FAIL : LX_OK;
 }
 
 lx_status lx_simulate_grid(lx_network net, int64_t P, const double* theta, const int32_t* x0,
@@ -768,7 +801,12 @@ lx_status lx_simulate_grid(lx_network net, int64_t P, const double* theta, const
   L.prm.times = times;
   L.prm.x_grid = x_grid;
   L.prm.n_times = n_times;
-  return launch_sim(L, L.prm, theta, x0, x_out, r_out, G_out, stats, (hipStream_t)stream);
+  st = launch_sim(L, L.prm, theta, x0, x_out, r_out, G_out, stats, (hipStream_t)stream);
+  if (st != LX_OK) return st;
+  int64_t failed = 0;
+  st = check_lanes(o, P, stats, (hipStream_t)stream, &failed);
+  if (st != LX_OK) return st;
+  return failed ? LX_W_LANE_FAIL : LX_OK;
 }
 
 lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, double eps,
@@ -843,6 +881,19 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
   hipError_t e = hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)block, 1, 1, 0,
                                        (hipStream_t)stream, kargs, nullptr);
   if (e != hipSuccess) return hip_fail(e, "launch lx_sim_set");
+  int64_t failed_total = 0;
+  std::string first_msg;
+  for (int k = 0; k < K; ++k) {
+    int64_t failed = 0;
+    st = check_lanes(o, items[k].P, items[k].stats, (hipStream_t)stream, &failed);
+    if (st != LX_OK) return st;
+    if (failed && first_msg.empty()) first_msg = "item " + std::to_string(k) + ": " + g_err;
+    failed_total += failed;
+  }
+  if (failed_total) {
+    g_err = first_msg;
+    return LX_W_LANE_FAIL;
+  }
   return LX_OK;
 }
 

@@ -64,7 +64,7 @@ class Options(C.Structure):
         ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("block_size", C.c_int32),
         ("max_steps", C.c_int64), ("lanes_per_wave", C.c_int32), ("ssa_k", C.c_int32),
         ("blocks_per_cu", C.c_int32), ("pid_stride", C.c_uint32), ("regroup", C.c_int32), ("lanes_per_traj", C.c_int32), ("jacobian", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("check_lanes", C.c_int32), ("reserved", C.c_int32 * 2),
     ]
 
 
@@ -129,8 +129,19 @@ def lib():
     return _lib
 
 
+class LaneFailWarning(UserWarning):
+    """Some trajectories ended with a status other than OK (check_lanes=1)."""
+
+
+LX_W_LANE_FAIL = 1
+
+
 def _check(rc: int, what: str):
-    if rc != 0:
+    if rc == LX_W_LANE_FAIL:
+        import warnings
+        msg = lib().lx_last_error().decode(errors="replace")
+        warnings.warn(f"{what}: {msg}", LaneFailWarning, stacklevel=3)
+    elif rc != 0:
         msg = lib().lx_last_error().decode(errors="replace")
         raise LxError(f"{what} failed ({rc}): {msg}")
 

@@ -461,3 +461,35 @@ def test_set_full_size_sampled(lxm, orc):
         nu = (net.p - net.m).astype(np.int64)
         ok = st["status"] == 0
         assert np.array_equal(got[k]["x"][ok], wl.x0[k][ok] + got[k]["r"][ok].astype(np.int64) @ nu)
+
+
+def test_check_lanes_reports_failed_trajectories(lxm):
+    import warnings
+    import torch
+    net = W.dimer()
+    P = 300
+    theta = W.gamma_prior_theta(net, P, seed=12)
+    _, x0 = W.tile(net, P)
+    bad = theta.copy()
+    bad[7] = -1.0
+    with pytest.warns(lxm.LaneFailWarning, match=r"1 of 300 trajectories .*row 7, status 3"):
+        gpu_run(lxm, net, bad, x0, 1.0, "adaptive", check_lanes=1)
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")
+        gpu_run(lxm, net, theta, x0, 1.0, "adaptive", check_lanes=1, schedule="batched")
+    h = _handle(lxm, net)
+    with pytest.raises(lxm.LxError):
+        lxm.simulate(h, torch.as_tensor(theta, device="cuda"), torch.as_tensor(x0, device="cuda"),
+                     1.0, with_stats=False, check_lanes=1)
+    # observation times and network sets report the same way
+    tt = torch.as_tensor(np.array([0.5, 1.0]), device="cuda")
+    with pytest.warns(lxm.LaneFailWarning, match=r"row 7"):
+        lxm.simulate_grid(h, torch.as_tensor(bad, device="cuda"), torch.as_tensor(x0, device="cuda"),
+                          tt, check_lanes=1)
+    items = [dict(net=h, theta=torch.as_tensor(theta, device="cuda"),
+                  x0=torch.as_tensor(x0, device="cuda")),
+             dict(net=h, theta=torch.as_tensor(bad, device="cuda"),
+                  x0=torch.as_tensor(x0, device="cuda"), pid_base=P)]
+    with pytest.warns(lxm.LaneFailWarning, match=r"item 1: 1 of 300"):
+        lxm.simulate_set(items, 1.0, check_lanes=1)
+    torch.cuda.synchronize()
