@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="repeat the oracle sample until this much time has passed")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--untuned", action="store_true", help="ignore autotuned batched knobs")
     ap.add_argument("--workload", default="dimer", choices=sorted(WORKLOADS),
@@ -184,6 +186,18 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
     }
 
 
+def repeat_timed(run, min_seconds):
+    """Run `run()` until at least `min_seconds` have passed (at least once);
+    returns (first result, repetitions, seconds)."""
+    t0 = time.perf_counter()
+    first = run()
+    reps = 1
+    while time.perf_counter() - t0 < min_seconds:
+        run()
+        reps += 1
+    return first, reps, time.perf_counter() - t0
+
+
 def observation_times(torch, args, wl):
     """--times K: K evenly spaced times ending at t_end (device tensor), or None."""
     if not args.times:
@@ -263,14 +277,17 @@ def bench_set(args, torch, lx, W):
         import oracle
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
         n_cpu = args.cpu_sample or 8192
-        t0 = time.perf_counter()
-        for k, net in enumerate(wl.nets):
-            oracle.simulate(net.m, net.p, wl.theta[k][:n_cpu], wl.x0[k][:n_cpu], wl.t_end,
-                            mode=wl.mode, nthreads=nth, pid_base=k, pid_stride=len(wl.nets))
-        dt = time.perf_counter() - t0
-        cpu = {"value": len(wl.nets) * n_cpu / dt, "unit": "trajectories/s", "cores": nth,
+
+        def run():
+            for k, net in enumerate(wl.nets):
+                oracle.simulate(net.m, net.p, wl.theta[k][:n_cpu], wl.x0[k][:n_cpu], wl.t_end,
+                                mode=wl.mode, nthreads=nth, pid_base=k, pid_stride=len(wl.nets))
+
+        _, reps, dt = repeat_timed(run, args.cpu_seconds)
+        cpu = {"value": reps * len(wl.nets) * n_cpu / dt, "unit": "trajectories/s", "cores": nth,
                "kind": "oracle", "sample": f"the first {n_cpu} trajectories of each network, "
-                                           f"fp64 oracle, {nth} threads, {dt:.1f} s"}
+                                           f"fp64 oracle, {nth} threads, {reps} x in {dt:.1f} s",
+               "per_core": reps * len(wl.nets) * n_cpu / dt / nth}
     line(args, "trajectories/s", hr["trajectories_per_s"], hr["ms_per_step"],
          "f32+f64" if hr["precision"] == "mixed" else "f64",
          {"workload": wl.name, "trajectories": wl.P, "t_end": wl.t_end, "eps": wl.eps,
@@ -340,13 +357,14 @@ def bench_pf(args, torch, lx, W):
         import oracle
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
         n_cpu = args.cpu_sample or 65536
-        t0 = time.perf_counter()
-        oracle.pf_run(net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu], K, dt, obs, sd, y,
-                      np.full(net.M, 2.0), 2.0 / net.theta, nthreads=nth)
-        dtc = time.perf_counter() - t0
-        cpu = {"value": n_cpu * K / dtc, "unit": "particle-intervals/s", "cores": nth,
+        _, reps, dtc = repeat_timed(
+            lambda: oracle.pf_run(net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu], K, dt, obs,
+                                  sd, y, np.full(net.M, 2.0), 2.0 / net.theta, nthreads=nth),
+            args.cpu_seconds)
+        cpu = {"value": reps * n_cpu * K / dtc, "unit": "particle-intervals/s", "cores": nth,
                "kind": "oracle", "sample": f"{n_cpu} particles x {K} intervals, fp64 oracle "
-                                           f"filter, {dtc:.1f} s"}
+                                           f"filter, {nth} threads, {reps} x in {dtc:.1f} s",
+               "per_core": reps * n_cpu * K / dtc / nth}
     line(args, "particle-intervals/s", hr["particle_intervals_per_s"], hr["ms_per_step"],
          "f32+f64" if hr["precision"] == "mixed" else "f64",
          {"workload": wl.name, "particles": wl.P, "intervals": K, "dt": dt, "form": head},
@@ -412,23 +430,26 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
-        t0 = time.perf_counter()
         n_cpu = args.cpu_sample or (wl.P if args.workload == "dimer" else min(wl.P, 1024))
-        if args.times:
-            import numpy as np
-            ref = oracle.simulate_grid(net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu],
-                                       np.linspace(wl.t_end / args.times, wl.t_end, args.times),
-                                       mode=wl.mode, nthreads=nth)
-        else:
-            ref = oracle.simulate(net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu], wl.t_end,
-                                  mode=wl.mode, nthreads=nth)
-        dt = time.perf_counter() - t0
+
+        def run():
+            if args.times:
+                import numpy as np
+                return oracle.simulate_grid(
+                    net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu],
+                    np.linspace(wl.t_end / args.times, wl.t_end, args.times), mode=wl.mode,
+                    nthreads=nth)
+            return oracle.simulate(net.m, net.p, wl.theta[0][:n_cpu], wl.x0[0][:n_cpu],
+                                   wl.t_end, mode=wl.mode, nthreads=nth)
+
+        ref, reps, dt = repeat_timed(run, args.cpu_seconds)
         ops_per_traj = float(ref["stats"]["ops"].mean())
         what = (f"all {wl.P} trajectories of the workload" if n_cpu == wl.P else
                 f"the first {n_cpu} of the {wl.P} trajectories")
-        cpu = {"value": n_cpu / dt, "unit": "trajectories/s", "cores": nth, "kind": "oracle",
-               "sample": f"{what}, fp64 oracle, {nth} threads, {dt:.1f} s",
-               "per_core": n_cpu / dt / nth}
+        cpu = {"value": reps * n_cpu / dt, "unit": "trajectories/s", "cores": nth,
+               "kind": "oracle",
+               "sample": f"{what}, fp64 oracle, {nth} threads, {reps} x in {dt:.1f} s",
+               "per_core": reps * n_cpu / dt / nth}
         log(args, f"[bench] oracle: {cpu}")
     roof = None
     if ops_per_traj is not None:

@@ -35,3 +35,13 @@ def test_kernel_id_tracks_options_and_traffic_records_are_keyed():
                 assert rec["fetch_bytes"] > 0 and rec["write_bytes"] > 0
                 assert bench.recorded_traffic(rec["kernel_id"])[0] == (rec["fetch_bytes"]
                                                                        + rec["write_bytes"])
+
+
+def test_repeat_timed_runs_until_the_time_has_passed():
+    import time
+    import bench
+    calls = []
+    first, reps, secs = bench.repeat_timed(lambda: calls.append(1) or len(calls), 0.2)
+    assert first == 1 and reps == len(calls) and reps >= 2 and secs >= 0.2
+    first, reps, _ = bench.repeat_timed(lambda: time.sleep(0.05) or "x", 0.0)
+    assert first == "x" and reps == 1
