@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--times", type=int, default=0,
                     help="record the states at this many evenly spaced observation times "
                          "(lx_simulate_grid) instead of only at t_end")
+    ap.add_argument("--segments", type=int, default=1,
+                    help="run each step as this many consecutive launches over equal parts of "
+                         "[0, t_end] (state, r and G carried on, random stream = part); for "
+                         "horizons too long for one launch")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="trajectories the oracle baseline runs (default: all for the dimer, "
                          "1024 otherwise)")
@@ -142,14 +146,42 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
         opts.update(json.loads(args.options))
     stream = torch.cuda.current_stream()
     grid_times = observation_times(torch, args, wl)
+    segs = max(1, args.segments)
+    totals = {}
+    if segs > 1:
+        x_cur = torch.empty_like(x0)
 
     def launch():
-        if grid_times is None:
+        if segs > 1:
+            # consecutive launches over equal parts of [0, t_end]; the per-part
+            # statistics are read back after each part (a few MB) and summed
+            x_cur.copy_(x0)
+            out["r"].zero_()
+            out["G"].zero_()
+            totals.clear()
+            for k in range(segs):
+                lx.simulate(h, theta, x_cur, wl.t_end * (k + 1) / segs, wl.eps, wl.mode, out=out,
+                            stream=stream, t_start=wl.t_end * k / segs, accumulate=1,
+                            rng_stream=k, **opts)
+                x_cur.copy_(out["x"])
+                st = lx.stats_numpy(out["stats"])
+                for f in ("attempts", "steps_ssa", "steps_explicit", "steps_implicit",
+                          "rejections"):
+                    totals[f] = totals.get(f, 0) + st[f].astype("int64")
+                totals["bad"] = totals.get("bad", 0) + int((st["status"] != 0).sum())
+                log(args, f"[bench] part {k + 1}/{segs} done")
+        elif grid_times is None:
             lx.simulate(h, theta, x0, wl.t_end, wl.eps, wl.mode, out=out, stream=stream, **opts)
         else:
             lx.simulate_grid(h, theta, x0, grid_times, wl.eps, wl.mode, out=out, stream=stream,
                              **opts)
 
+    if segs > 1:
+        # compile the accumulating kernel outside the timed region (64 lanes, a
+        # sliver of the first part)
+        n = min(64, wl.P)
+        lx.simulate(h, theta[:n].contiguous(), x0[:n].contiguous(), wl.t_end / segs / 1000.0,
+                    wl.eps, wl.mode, stream=stream, accumulate=1, **opts)
     for _ in range(args.warmup):
         launch()
     torch.cuda.synchronize()
@@ -166,8 +198,14 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
     ms = sum(per) / len(per)
     r_total = int(out["r"].sum(dtype=torch.int64).item())
     stats = lx.stats_numpy(out["stats"])
+    if segs > 1:
+        import numpy as np
+        stats = {f: totals[f] for f in ("attempts", "steps_ssa", "steps_explicit",
+                                        "steps_implicit", "rejections")}
+        stats["status"] = np.full(1, 0 if totals["bad"] == 0 else 1)
     return {
-        "kernel_id": kernel_id(dict(opts, observation_times=args.times) if args.times else opts),
+        "kernel_id": kernel_id(dict(opts, observation_times=args.times) if args.times else
+                               dict(opts, segments=segs) if segs > 1 else opts),
         "ms_per_step": ms,
         "wall_s": wall,
         "trajectories_per_s": wl.P / (ms / 1e3),
@@ -385,8 +423,10 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
-    if args.times and args.workload in ("mixed_set", "telegraph_pf"):
-        raise SystemExit("--times applies to single-network workloads")
+    if (args.times or args.segments > 1) and args.workload in ("mixed_set", "telegraph_pf"):
+        raise SystemExit("--times and --segments apply to single-network workloads")
+    if args.times and args.segments > 1:
+        raise SystemExit("--times and --segments are exclusive")
     if args.workload == "mixed_set":
         return bench_set(args, torch, lx, W)
     if args.workload == "telegraph_pf":
@@ -490,6 +530,8 @@ def main():
     }
     if args.times:
         line["config"]["observation_times"] = args.times
+    if args.segments > 1:
+        line["config"]["segments"] = args.segments
     print(json.dumps(line), flush=True)
 
 
