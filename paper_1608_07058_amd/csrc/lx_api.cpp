@@ -355,8 +355,6 @@ lx_status check_device(int* dev_out) {
   return LX_OK;
 }
 
-// Fetch (compiling on first use) a kernel of the network for the current
-// device.  variant: "plain", "batched" or "hooks"; precision LX_PREC_*.
 // Fetch (compiling and loading on first use) a kernel for the current device
 // from the cache of network `owner`; `make_src` produces its source.
 template <class F>
@@ -389,6 +387,8 @@ lx_status get_kernel_src(lx_network_s* owner, const std::string& variant_key, F 
   return LX_OK;
 }
 
+// A simulation or hook kernel of one network: variant "plain", "batched",
+// "large" or "hooks", precision LX_PREC_*, `grid` for observation times.
 lx_status get_kernel(lx_network_s* net, const char* variant, int precision, int block,
                      const char* fname, hipFunction_t* fn, int tpl, const std::string& consts,
                      bool grid = false) {
