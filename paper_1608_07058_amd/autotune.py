@@ -25,7 +25,7 @@ DEFAULT_FILE = os.path.join(HERE, "tuned.json")
 GRID = {
     "lanes_per_traj": (1, 2, 4, 8, 16),
     "lanes_per_wave": (16, 32, 64),
-    "ssa_k": (4, 8, 16),
+    "ssa_k": (4, 8, 16, 64),
     "block_size": (64, 256),
     "blocks_per_cu": (2, 4),
     "regroup": (0,),

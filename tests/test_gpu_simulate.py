@@ -177,12 +177,23 @@ def test_full_size_dimer_sampled(lxm, orc, precision, schedule):
     assert np.all(got["x"] >= 0) and np.all(got["stats"]["status"] == 0)
 
 
-def test_full_size_birth_death(lxm, orc):
+@pytest.mark.parametrize("form", ["plain", "tuned_mixed", "tuned_fp64"])
+def test_full_size_birth_death(lxm, orc, form):
+    # the benchmark ensemble in the plain form and in the tuned batched launch
+    # (the knobs autotune.py recorded: 16-lane groups, ssa_k 64)
+    from paper_1608_07058_amd import autotune
     wl = W.birth_death_workload()
     net = wl.nets[0]
-    got = gpu_run(lxm, net, wl.theta[0], wl.x0[0], wl.t_end, wl.mode)
-    ref = orc.simulate(net.m, net.p, wl.theta[0], wl.x0[0], wl.t_end, mode=wl.mode)
-    assert_same(got, ref, "birth-death 1024")
+    precision = "mixed" if form == "tuned_mixed" else "fp64"
+    opts = dict(precision=precision)
+    if form != "plain":
+        opts.update(schedule="batched",
+                    **autotune.lookup(net.m, net.p, wl.P, precision, wl.mode))
+        assert opts.get("lanes_per_traj", 1) > 1
+    got = gpu_run(lxm, net, wl.theta[0], wl.x0[0], wl.t_end, wl.mode, **opts)
+    ref = orc.simulate(net.m, net.p, wl.theta[0], wl.x0[0], wl.t_end, mode=wl.mode,
+                       precision=precision)
+    assert_same(got, ref, f"birth-death 1024 {form}")
 
 
 def test_edge_cases(lxm, orc):
