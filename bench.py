@@ -139,7 +139,8 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
     if opts["schedule"] == "batched" and not args.untuned:
         # knobs found by paper_1608_07058_amd/autotune.py for this ensemble, if any
         net = wl.nets[0]
-        opts.update(autotune.lookup(net.m, net.p, wl.P, opts["precision"], wl.mode))
+        opts.update(autotune.lookup(net.m, net.p, wl.P, opts["precision"], wl.mode,
+                                    wl.theta[0], wl.x0[0]))
     if args.block_size:
         opts["block_size"] = args.block_size
     if args.options:

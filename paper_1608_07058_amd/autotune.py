@@ -41,11 +41,16 @@ def valid(opts, P):
     return (opts["lanes_per_wave"] // tpl) * (opts["block_size"] // 64) <= P
 
 
-def key_of(net_m, net_p, P, precision, mode, arch="gfx950"):
+def key_of(net_m, net_p, P, precision, mode, theta, x0, arch="gfx950"):
+    """Key of an ensemble: the network, its inputs (theta [P][M], x0 [P][N]:
+    two ensembles of one network with other constants behave differently),
+    P, precision and mode."""
     import numpy as np
     h = hashlib.sha1(np.ascontiguousarray(net_m, np.int32).tobytes() +
                      np.ascontiguousarray(net_p, np.int32).tobytes()).hexdigest()[:16]
-    return f"{arch}/{h}/P{P}/{precision}/{mode}"
+    d = hashlib.sha1(np.ascontiguousarray(theta, np.float64).tobytes() +
+                     np.ascontiguousarray(x0, np.int32).tobytes()).hexdigest()[:8]
+    return f"{arch}/{h}-{d}/P{P}/{precision}/{mode}"
 
 
 def load(path=DEFAULT_FILE):
@@ -55,9 +60,10 @@ def load(path=DEFAULT_FILE):
         return json.load(f)
 
 
-def lookup(net_m, net_p, P, precision, mode, path=DEFAULT_FILE):
+def lookup(net_m, net_p, P, precision, mode, theta, x0, path=DEFAULT_FILE):
     """Tuned options for this ensemble, or {} if it was never tuned."""
-    return dict(load(path).get(key_of(net_m, net_p, P, precision, mode), {}).get("options", {}))
+    key = key_of(net_m, net_p, P, precision, mode, theta, x0)
+    return dict(load(path).get(key, {}).get("options", {}))
 
 
 def tune(lx, h, theta, x0, t_end, eps, mode, precision, grid=None, reps=2, log=None):
@@ -167,7 +173,7 @@ def save(key, options, ms, table, path=DEFAULT_FILE):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--workload", default="dimer",
-                    choices=("dimer", "birth_death", "telegraph", "mixed_set"))
+                    choices=("dimer", "birth_death", "telegraph", "mixed_set", "dimer_rathinam"))
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--out", default=DEFAULT_FILE)
     args = ap.parse_args()
@@ -177,7 +183,8 @@ def main():
     if args.workload == "mixed_set":
         return main_set(args, torch, lx, W)
     wl = {"dimer": W.dimer_workload, "birth_death": W.birth_death_workload,
-          "telegraph": W.telegraph_workload}[args.workload]()
+          "telegraph": W.telegraph_workload,
+          "dimer_rathinam": W.rathinam_workload}[args.workload]()
     net = wl.nets[0]
     h = lx.Network(net.m, net.p)
     theta = torch.as_tensor(wl.theta[0], device="cuda")
@@ -185,7 +192,7 @@ def main():
     best, table = tune(lx, h, theta, x0, wl.t_end, wl.eps, wl.mode, args.precision,
                        log=lambda s: print(s, flush=True))
     ms = min(t for _, t in table)
-    key = key_of(net.m, net.p, wl.P, args.precision, wl.mode)
+    key = key_of(net.m, net.p, wl.P, args.precision, wl.mode, wl.theta[0], wl.x0[0])
     save(key, best, ms, table, args.out)
     print(json.dumps({"key": key, "best": best, "ms": ms}), flush=True)
 

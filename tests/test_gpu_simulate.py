@@ -161,7 +161,8 @@ def test_full_size_dimer_sampled(lxm, orc, precision, schedule):
     kw = dict(schedule=schedule)
     if schedule == "tuned":  # the knobs the benchmark uses
         from paper_1608_07058_amd import autotune
-        kw = dict(schedule="batched", **autotune.lookup(net.m, net.p, wl.P, precision, wl.mode))
+        kw = dict(schedule="batched", **autotune.lookup(net.m, net.p, wl.P, precision, wl.mode,
+                                                        wl.theta[0], wl.x0[0]))
     got = gpu_run(lxm, net, theta, x0, wl.t_end, wl.mode, precision=precision, **kw)
     rng = np.random.default_rng(5)
     sample = np.concatenate([[0, 63, 64, wl.P - 1], rng.choice(wl.P, 60, replace=False)])
@@ -188,7 +189,8 @@ def test_full_size_birth_death(lxm, orc, form):
     opts = dict(precision=precision)
     if form != "plain":
         opts.update(schedule="batched",
-                    **autotune.lookup(net.m, net.p, wl.P, precision, wl.mode))
+                    **autotune.lookup(net.m, net.p, wl.P, precision, wl.mode, wl.theta[0],
+                                      wl.x0[0]))
         assert opts.get("lanes_per_traj", 1) > 1
     got = gpu_run(lxm, net, wl.theta[0], wl.x0[0], wl.t_end, wl.mode, **opts)
     ref = orc.simulate(net.m, net.p, wl.theta[0], wl.x0[0], wl.t_end, mode=wl.mode,
