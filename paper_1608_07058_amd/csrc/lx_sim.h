@@ -82,11 +82,29 @@ __device__ __forceinline__ double dg_of(int j, int k, const double (&y)[NET::N])
 
 // Cross-lane read within groups of TPL lanes (lane s of the caller's group).
 // Groups of 2 and 4 lanes lie within a quad of the wave, so the read is a
-// DPP quad permutation (a VALU move, no LDS round trip); `s` is a
-// compile-time constant after unrolling, so the switch folds to one case.
+// DPP quad permutation (a VALU move, no LDS round trip); a group of 16 is a
+// DPP row, read with a row broadcast, and a group of 8 is half a row, read
+// with two row broadcasts whose bank masks select the half.  `s` is a
+// compile-time constant after unrolling, so the branches fold away.
+template <int W, int S = 0>
+__device__ __forceinline__ int row_group_read(int v, int s) {
+  if constexpr (S + 1 < W) {
+    if (s != S) return row_group_read<W, S + 1>(v, s);
+  }
+  if constexpr (W == 16) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x150 + S, 0xF, 0xF, false);  // row_newbcast:S
+  } else {
+    // lanes 0-7 of the row (banks 0, 1) read lane S, lanes 8-15 lane 8 + S
+    const int lo = __builtin_amdgcn_update_dpp(0, v, 0x150 + S, 0xF, 0x3, false);
+    return __builtin_amdgcn_update_dpp(lo, v, 0x158 + S, 0xF, 0xC, false);
+  }
+}
+
 template <int TPL>
 __device__ __forceinline__ int group_read_b32(int v, int s) {
-  if constexpr (TPL == 4) {
+  if constexpr (TPL == 16 || TPL == 8) {
+    return row_group_read<TPL>(v, s);
+  } else if constexpr (TPL == 4) {
     switch (s) {
       case 0: return __builtin_amdgcn_update_dpp(0, v, 0x00, 0xF, 0xF, false);
       case 1: return __builtin_amdgcn_update_dpp(0, v, 0x55, 0xF, 0xF, false);
@@ -103,7 +121,7 @@ __device__ __forceinline__ int group_read_b32(int v, int s) {
 
 template <int TPL, class T>
 __device__ __forceinline__ T group_read(T v, int s) {
-  if constexpr (TPL == 2 || TPL == 4) {
+  if constexpr (TPL == 2 || TPL == 4 || TPL == 8 || TPL == 16) {
     if constexpr (sizeof(T) == 4) {
       return __builtin_bit_cast(T, group_read_b32<TPL>(__builtin_bit_cast(int, v), s));
     } else {
