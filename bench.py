@@ -1,12 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark: trajectories/s and reaction-events/s on one MI355X.
 
-A step is one ``lx_simulate`` call over the whole ensemble of the
-decaying-dimerizing workload (16384 trajectories, X0 = (10000, 0, 0),
-t_end = 30, eps = 0.03, adaptive explicit/implicit/SSA): every step of the
-method runs inside it, inputs resident in HBM, outputs preallocated.  The
-headline form is the batched mixed-precision schedule; the plain fp64 form
-(one lane per trajectory for life) is timed beside it.
+A step advances the whole ensemble of the batched-particles workload to its
+final time: 2^20 trajectories, particle p running network p mod 3 of
+isomerisation (N_total 1000), birth-death and the bistable Schloegl network,
+theta per particle from Gamma(2, 2/theta_nominal) priors, t_end = 50,
+eps = 0.03, adaptive explicit/implicit/SSA.  Every step of the method runs
+inside it, inputs resident in HBM, outputs preallocated.  The headline form is
+the batched mixed-precision schedule (one launch, lx_simulate_set); the plain
+fp64 form (one plain lx_simulate launch per network, one lane per trajectory
+for life) is timed beside it.  Throughput counts the trajectories that end in
+status OK; the others are reported by status.  ``--workload`` selects the
+secondary single-network workloads and the particle filter.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on one
 GPU.
@@ -32,7 +37,7 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Device sources compiled into the simulation kernels at run time.
 KERNEL_SOURCES = ("lx_params.h", "lx_device.h", "lx_sim.h")
 PROFILES = os.path.join(ROOT, "profiles")
-# Single-network workloads bench.py can time; the headline line is "dimer".
+# Workloads bench.py can time; the headline line is "mixed_set".
 WORKLOADS = {
     "dimer": "dimer_workload",
     "birth_death": "birth_death_workload",
@@ -52,9 +57,11 @@ FORMS = {
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="batched_mixed,plain_fp64,plain_mixed,batched_fp64")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--forms", default="",
+                    help="comma-separated forms (default: batched_mixed,plain_fp64,batched_fp64 "
+                         "for the set, all four for single networks)")
     ap.add_argument("--headline", default="batched_mixed")
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -63,8 +70,9 @@ def parse():
                     help="repeat the oracle sample until this much time has passed")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--untuned", action="store_true", help="ignore autotuned batched knobs")
-    ap.add_argument("--workload", default="dimer", choices=sorted(WORKLOADS),
-                    help="dimer (the headline, default) or a secondary single-network workload")
+    ap.add_argument("--workload", default="mixed_set", choices=sorted(WORKLOADS),
+                    help="mixed_set (the headline, default), a secondary single-network "
+                         "workload, or the particle filter (telegraph_pf)")
     ap.add_argument("--t-end", type=float, default=0.0,
                     help="override the workload's t_end (secondary workloads only)")
     ap.add_argument("--options", default="",
@@ -77,8 +85,8 @@ def parse():
                          "[0, t_end] (state, r and G carried on, random stream = part); for "
                          "horizons too long for one launch")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="trajectories the oracle baseline runs (default: all for the dimer, "
-                         "1024 otherwise)")
+                    help="trajectories the oracle baseline runs (default: 8192 per network for "
+                         "the set, all for the dimer, 1024 otherwise)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes --steps times "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -274,65 +282,136 @@ def line(args, metric_unit, value, ms, dtype, config, extra):
     print(json.dumps(out), flush=True)
 
 
+def status_counts(lx, stats_list):
+    """Trajectories per final status over a list of lx_stats tensors."""
+    import numpy as np
+    cnt = np.zeros(5, np.int64)
+    for st in stats_list:
+        cnt += np.bincount(lx.stats_numpy(st)["status"], minlength=5)[:5]
+    return {lx.LANE_STATUS[k]: int(c) for k, c in enumerate(cnt) if c}
+
+
+def set_roofline(hr, ops_per_launch, ops_note, P, kid):
+    """Roofline of the set kernel: algorithmic lane-operations of one launch
+    (oracle count per network x trajectories) over its mean duration."""
+    achieved = ops_per_launch / (hr["ms_per_step"] / 1e3) / 1e12
+    rec = recorded_traffic(kid)
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_TOPS, "traffic": rec[0] if rec else None,
+            "traffic_unit": "bytes per launch", "traffic_source": rec[1] if rec else None,
+            "ops_per_launch": ops_per_launch, "ops_source": ops_note,
+            "kernel": "lx_sim_set", "kernel_id": kid}
+
+
 def bench_set(args, torch, lx, W):
-    """Three networks in one launch (lx_simulate_set): particle p runs network
-    p mod 3 (its RNG particle id), batched schedule."""
+    """Three networks in one ensemble: 2^20 trajectories, particle p runs
+    network p mod 3 (its RNG particle id).  The batched forms run the whole
+    ensemble in one launch (lx_simulate_set); the plain forms run one plain
+    lx_simulate launch per network (one lane per trajectory for life), all on
+    the same stream, inside the same timed step."""
+    import numpy as np
     wl = W.mixed_set_workload()
     hs = [lx.Network(n.m, n.p) for n in wl.nets]
     th = [torch.as_tensor(t, device="cuda") for t in wl.theta]
     xx = [torch.as_tensor(x, device="cuda") for x in wl.x0]
-    outs = [None] * len(hs)
-    results = {}
+    K = len(hs)
     from paper_1608_07058_amd import autotune
-    for form in [f for f in args.forms.split(",") if f.startswith("batched")]:
+    stream = torch.cuda.current_stream()
+    results = {}
+    for form in [f for f in args.forms.split(",") if f]:
         opts = dict(FORMS[form])
-        opts.pop("schedule")
-        if not args.untuned:
+        sched = opts.pop("schedule")
+        if sched == "batched" and not args.untuned:
             # knobs found by paper_1608_07058_amd/autotune.py for this set, if any
             opts.update(autotune.lookup_set([(n.m, n.p) for n in wl.nets], wl.P,
                                             opts["precision"], wl.mode))
         if args.options:
             opts.update(json.loads(args.options))
-        stream = torch.cuda.current_stream()
+        outs = [{"x": torch.empty((t.shape[0], n.N), dtype=torch.int32, device="cuda"),
+                 "r": torch.zeros((t.shape[0], n.M), dtype=torch.int32, device="cuda"),
+                 "G": torch.zeros((t.shape[0], n.M), dtype=torch.float64, device="cuda"),
+                 "stats": torch.empty((t.shape[0], lx.STATS_WORDS), dtype=torch.int64,
+                                      device="cuda")}
+                for t, n in zip(th, wl.nets)]
 
-        def launch():
-            items = [{"net": h, "theta": t, "x0": x, "pid_base": k, "pid_stride": len(hs),
-                      "out": outs[k]} for k, (h, t, x) in enumerate(zip(hs, th, xx))]
-            res = lx.simulate_set(items, wl.t_end, wl.eps, wl.mode, stream=stream, **opts)
-            for k in range(len(hs)):
-                outs[k] = res[k]
+        if sched == "batched":
+            def launch():
+                items = [{"net": h, "theta": t, "x0": x, "pid_base": k, "pid_stride": K,
+                          "out": outs[k]} for k, (h, t, x) in enumerate(zip(hs, th, xx))]
+                lx.simulate_set(items, wl.t_end, wl.eps, wl.mode, stream=stream, **opts)
+        else:
+            def launch():
+                for k in range(K):
+                    lx.simulate(hs[k], th[k], xx[k], wl.t_end, wl.eps, wl.mode, out=outs[k],
+                                stream=stream, schedule="plain", pid_base=k, pid_stride=K,
+                                **opts)
 
         ms, wall = timed(args, torch, launch, stream)
-        r_total = sum(int(o["r"].sum(dtype=torch.int64).item()) for o in outs)
-        ok = all(bool((lx.stats_numpy(o["stats"])["status"] == 0).all()) for o in outs)
-        results[form] = {"ms_per_step": ms, "wall_s": wall, "trajectories_per_s": wl.P / (ms / 1e3),
-                         "events_per_s": r_total / (ms / 1e3), "lane_status_ok": ok,
-                         "precision": opts["precision"], "options": opts}
+        counts = status_counts(lx, [o["stats"] for o in outs])
+        n_ok = counts.get("OK", 0)
+        ev_ok = 0
+        for o in outs:
+            ok = (lx.stats_numpy(o["stats"])["status"] == 0)
+            ev_ok += int(o["r"].sum(dim=1, dtype=torch.int64).cpu().numpy()[ok].sum())
+        results[form] = {"ms_per_step": ms, "wall_s": wall,
+                         "trajectories_per_s": n_ok / (ms / 1e3),
+                         "events_per_s": ev_ok / (ms / 1e3),
+                         "status_counts": counts,
+                         "precision": opts["precision"], "schedule": sched,
+                         "kernel_id": kernel_id(dict(opts, schedule=sched, workload="mixed_set")),
+                         "options": {k: v for k, v in opts.items() if k != "precision"}}
         log(args, f"[bench] {form}: {results[form]}")
     head = args.headline if args.headline in results else sorted(results)[0]
     hr = results[head]
     cpu = None
+    roof = None
     if not args.no_cpu_baseline:
         import oracle
         nth = args.cpu_threads or min(os.cpu_count() or 1, 16)
         n_cpu = args.cpu_sample or 8192
+        subs = [min(n_cpu, t.shape[0]) for t in wl.theta]
 
-        def run():
-            for k, net in enumerate(wl.nets):
-                oracle.simulate(net.m, net.p, wl.theta[k][:n_cpu], wl.x0[k][:n_cpu], wl.t_end,
-                                mode=wl.mode, nthreads=nth, pid_base=k, pid_stride=len(wl.nets))
+        def run(precision="fp64"):
+            return [oracle.simulate(net.m, net.p, wl.theta[k][:subs[k]], wl.x0[k][:subs[k]],
+                                    wl.t_end, mode=wl.mode, nthreads=nth, pid_base=k,
+                                    pid_stride=K, precision=precision)
+                    for k, net in enumerate(wl.nets)]
 
-        _, reps, dt = repeat_timed(run, args.cpu_seconds)
-        cpu = {"value": reps * len(wl.nets) * n_cpu / dt, "unit": "trajectories/s", "cores": nth,
-               "kind": "oracle", "sample": f"the first {n_cpu} trajectories of each network, "
-                                           f"fp64 oracle, {nth} threads, {reps} x in {dt:.1f} s",
-               "per_core": reps * len(wl.nets) * n_cpu / dt / nth}
+        ref, reps, dt = repeat_timed(run, args.cpu_seconds)
+        cpu = {"value": reps * sum(subs) / dt, "unit": "trajectories/s", "cores": nth,
+               "kind": "oracle", "sample": f"the first {n_cpu} trajectories of each network "
+                                           f"(fp64 oracle, {nth} threads, {reps} x in {dt:.1f} s)",
+               "per_core": reps * sum(subs) / dt / nth}
+        log(args, f"[bench] oracle: {cpu}")
+        # algorithmic work of the headline launch: the oracle's operation count
+        # of the same trajectories in the headline's precision, mean per
+        # network over the sample, times the network's trajectories
+        if hr["precision"] != "fp64":
+            ref = run(hr["precision"])
+        ops = 0.0
+        se2 = 0.0
+        for k, r in enumerate(ref):
+            o = r["stats"]["ops"].astype(np.float64)
+            Pk = wl.theta[k].shape[0]
+            ops += o.mean() * Pk
+            se2 += (o.std() / math.sqrt(len(o)) * Pk) ** 2
+        roof = set_roofline(hr, ops, f"oracle operation count ({hr['precision']}) of the first "
+                                     f"{n_cpu} trajectories of each network, scaled to the "
+                                     f"ensemble; sampling SE {100 * math.sqrt(se2) / ops:.1f} %",
+                            wl.P, hr["kernel_id"])
+    plain = results.get("plain_fp64", {})
     line(args, "trajectories/s", hr["trajectories_per_s"], hr["ms_per_step"],
          "f32+f64" if hr["precision"] == "mixed" else "f64",
          {"workload": wl.name, "trajectories": wl.P, "t_end": wl.t_end, "eps": wl.eps,
-          "mode": wl.mode, "form": head},
-         {"events_per_s": hr["events_per_s"], "forms": results, "roofline": None,
-          "cpu_baseline": cpu})
+          "mode": wl.mode, "form": head, "precision": hr["precision"],
+          "schedule": hr["schedule"],
+          "counted": "trajectories ending in status OK; the others are listed in "
+                     "status_counts"},
+         {"events_per_s": hr["events_per_s"], "status_counts": hr["status_counts"],
+          "forms": results,
+          "speedup_vs_plain_fp64": (hr["trajectories_per_s"] / plain["trajectories_per_s"]
+                                    if "trajectories_per_s" in plain else None),
+          "roofline": roof, "cpu_baseline": cpu})
 
 
 def bench_pf(args, torch, lx, W):
@@ -428,13 +507,16 @@ def main():
         raise SystemExit("--times and --segments apply to single-network workloads")
     if args.times and args.segments > 1:
         raise SystemExit("--times and --segments are exclusive")
+    if not args.forms:
+        args.forms = ("batched_mixed,plain_fp64,batched_fp64" if args.workload == "mixed_set"
+                      else "batched_mixed,plain_fp64,plain_mixed,batched_fp64")
     if args.workload == "mixed_set":
         return bench_set(args, torch, lx, W)
     if args.workload == "telegraph_pf":
         return bench_pf(args, torch, lx, W)
     wl = getattr(W, WORKLOADS[args.workload])()
     if args.t_end > 0.0:
-        if args.workload == "dimer":
+        if args.workload == "mixed_set":
             raise SystemExit("--t-end applies to secondary workloads only")
         wl.t_end = args.t_end
     net = wl.nets[0]

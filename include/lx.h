@@ -78,7 +78,8 @@ typedef int32_t lx_status;
 #define LX_LANE_OK 0
 #define LX_LANE_STEP_BUDGET 1     /* max_steps attempts used before t_end */
 #define LX_LANE_LAMBDA_OVERFLOW 2 /* a Poisson mean beyond the sampler's range
-                                     (2^30 in fp64, 2^22 in mixed) */
+                                     (2^30; in mixed precision means
+                                     from 2^22 are drawn in binary64) */
 #define LX_LANE_BAD_INPUT 3       /* negative/non-finite theta or negative x0 */
 #define LX_LANE_COUNT_OVERFLOW 4  /* a copy number or firing count beyond int32 */
 
@@ -134,8 +135,9 @@ typedef struct lx_options {
 
 /* Per-trajectory statistics (80 bytes). */
 typedef struct lx_stats {
-  int32_t status; /* LX_LANE_* */
-  int32_t pad;
+  int32_t status;      /* LX_LANE_* */
+  uint32_t crit_fired; /* accepted leaps in which a critical reaction fired
+                          (at most the attempts, so below 2^32) */
   double t_final; /* time reached (t_end unless status != OK) */
   int64_t steps_ssa, steps_explicit, steps_implicit; /* accepted actions by kind */
   int64_t rejections;   /* leap attempts rejected (negative state, failed solve) */

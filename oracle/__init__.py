@@ -45,7 +45,7 @@ class Options(C.Structure):
 
 
 STATS_DTYPE = np.dtype([
-    ("status", np.int32), ("pad", np.int32), ("t_final", np.float64),
+    ("status", np.int32), ("crit_fired", np.uint32), ("t_final", np.float64),
     ("steps_ssa", np.int64), ("steps_explicit", np.int64), ("steps_implicit", np.int64),
     ("rejections", np.int64), ("newton_iters", np.int64), ("newton_fail", np.int64),
     ("kclip", np.int64), ("attempts", np.int64), ("ops", np.int64),

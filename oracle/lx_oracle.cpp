@@ -269,6 +269,7 @@ struct PolicyF64 {
   // PTRS candidates per block of four words, and candidate s of a block
   static constexpr uint32_t TRIALS_PER_BLOCK = 1;
   static void candidate(const uint32_t w[4], uint32_t, R* u, R* v) { two_uniforms(w, u, v); }
+  static double wide_from() { return std::numeric_limits<double>::infinity(); }
   static double lambda_max() { return 1073741824.0; }  // 2^30
 };
 struct PolicyMixed {
@@ -287,7 +288,11 @@ struct PolicyMixed {
     *u = uniform_f32(w[2 * s]);
     *v = uniform_f32(w[2 * s + 1]);
   }
-  static double lambda_max() { return 4194304.0; }  // 2^22: float k stays exact
+  // binary32 holds every integer count exactly below 2^24; means at or above
+  // 2^22 are handed to the binary64 sampler (poisson_sample), so the range
+  // is binary64's
+  static double wide_from() { return 4194304.0; }  // 2^22
+  static double lambda_max() { return 1073741824.0; }  // 2^30
 };
 
 // log(1 + d) for d > -1 from the policy's log: u = 1 + d rounded, then
@@ -385,6 +390,11 @@ int64_t poisson_sample(typename P::R lam, typename P::R lam_thr, int kcap, const
   typedef typename P::R R;
   if (!(lam > (R)0)) return 0;
   if ((double)lam > P::lambda_max()) return -1;
+  // reading: in binary32 a mean of 2^22 or more is drawn by the binary64
+  // sampler at the same draw site (its counts near 2^24 would no longer be
+  // exact integers in binary32)
+  if ((double)lam >= P::wide_from())
+    return poisson_sample<PolicyF64>((double)lam, (double)lam_thr, kcap, rng, e, site);
   uint32_t w[4];
   if (lam < lam_thr) {
     rng.block(e, site, 0, w);
@@ -589,7 +599,8 @@ typedef struct {
 } orc_options;
 
 typedef struct {
-  int32_t status, pad;
+  int32_t status;
+  uint32_t crit_fired;  // accepted leaps in which a critical reaction fired
   double t_final;
   int64_t steps_ssa, steps_explicit, steps_implicit, rejections, newton_iters, newton_fail,
       kclip, attempts;
@@ -1070,6 +1081,7 @@ struct Traj {
           t = last ? t_end : t + tau;
           if (implicit) st.steps_implicit += 1;
           else st.steps_explicit += 1;
+          if (jc >= 0) st.crit_fired += 1;
           break;
         }
       }

@@ -163,9 +163,10 @@ def tune_set(lx, items, t_end, eps, mode, precision, grid=None, reps=1, log=None
 
 
 def save(key, options, ms, table, path=DEFAULT_FILE):
+    """Record the chosen knobs of `key`; the sweep itself (`table`) is printed
+    by the tuner, not stored with the package."""
     data = load(path)
-    data[key] = {"options": options, "ms": ms,
-                 "sweep": [{"options": o, "ms": t} for o, t in table]}
+    data[key] = {"options": options, "ms": ms}
     with open(path, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
 

@@ -227,6 +227,7 @@ struct F64 {
   __device__ static __forceinline__ void candidate(const Words4& w, u32, R* u, R* v) {
     uniforms(w, u, v);
   }
+  __device__ static __forceinline__ double wide_from() { return LX_INF_F64; }
   __device__ static __forceinline__ double lambda_max() { return 1073741824.0; }
   __device__ static __forceinline__ R inf() { return LX_INF_F64; }
 };
@@ -250,7 +251,11 @@ struct Mixed {
     *u = uniform_f32(s ? w.w2 : w.w0);
     *v = uniform_f32(s ? w.w3 : w.w1);
   }
-  __device__ static __forceinline__ double lambda_max() { return 4194304.0; }
+  // binary32 holds every integer count exactly below 2^24: means at or above
+  // 2^22 are drawn by the binary64 sampler (poisson_sample), so the range is
+  // binary64's
+  __device__ static __forceinline__ double wide_from() { return 4194304.0; }
+  __device__ static __forceinline__ double lambda_max() { return 1073741824.0; }
   __device__ static __forceinline__ R inf() { return LX_INF_F32; }
 };
 
@@ -433,6 +438,9 @@ __device__ __forceinline__ long long poisson_sample(typename P::R lam, typename 
   typedef typename P::R R;
   if (!(lam > (R)0)) return 0;
   if ((double)lam > P::lambda_max()) return -1;
+  if constexpr (P::mixed) {
+    if ((double)lam >= P::wide_from()) return poisson_ptrs<F64>((double)lam, key, pid, e, site);
+  }
   if (lam < lam_thr) return poisson_inversion<P>(lam, kcap, key, pid, e, site);
   return poisson_ptrs<P>(lam, key, pid, e, site);
 }

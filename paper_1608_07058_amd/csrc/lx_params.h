@@ -49,7 +49,8 @@ struct SimParams {
 #endif
 
 struct Stats {
-  int status, pad;
+  int status;
+  unsigned int crit_fired;  // accepted leaps in which a critical reaction fired
   double t_final;
   long long steps_ssa, steps_explicit, steps_implicit, rejections, newton_iters, newton_fail,
       kclip, attempts;

@@ -170,7 +170,7 @@ struct Lane {
   R tau_p;
   int ssa_left;
   // counters
-  u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip;  // < 2^32: attempts are bounded by max_steps
+  u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip, n_cf;  // < 2^32: attempts are bounded by max_steps
   long long n_nit;
 
   // The time the trajectory runs to now: t_end, or the next observation time.
@@ -213,7 +213,7 @@ struct Lane {
     gvalid = false;
     implicit = false;
     ssa_left = 0;
-    n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = 0;
+    n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = n_cf = 0;
   }
 
   __device__ __forceinline__ void store(long long p, int* x_out, int* r_out, double* G_out,
@@ -228,7 +228,7 @@ struct Lane {
     if (stats) {
       Stats s;
       s.status = status;
-      s.pad = 0;
+      s.crit_fired = n_cf;
       s.t_final = t;
       s.steps_ssa = n_ssa;
       s.steps_explicit = n_ex;
@@ -278,7 +278,7 @@ struct Lane {
   }
 
   // Number of 32-bit words of the state moved when lanes are regrouped.
-  static constexpr int STATE_WORDS = 20 + N + 3 * M + (GRID ? 3 : 0);
+  static constexpr int STATE_WORDS = 21 + N + 3 * M + (GRID ? 3 : 0);
 
   // Write the trajectory's state to an LDS slot (regrouping).  theta, g, a
   // and the plan's masks are not moved: they are reloaded or recomputed.
@@ -314,6 +314,7 @@ struct Lane {
     w[q++] = n_rej;
     w[q++] = n_nfail;
     w[q++] = n_clip;
+    w[q++] = n_cf;
     w[q++] = (u32)n_nit;
     w[q++] = (u32)((unsigned long long)n_nit >> 32);
     if constexpr (GRID) {
@@ -359,6 +360,7 @@ struct Lane {
     n_rej = w[q++];
     n_nfail = w[q++];
     n_clip = w[q++];
+    n_cf = w[q++];
     n_nit = (long long)((unsigned long long)w[q] | ((unsigned long long)w[q + 1] << 32));
     if constexpr (GRID) {
       q += 2;
@@ -873,6 +875,7 @@ struct Lane {
     t = last ? t_end_(prm) : t + tau;
     if (implicit) n_im += 1;
     else n_ex += 1;
+    n_cf += jc >= 0 ? 1u : 0u;
     plan = false;
     gvalid = true;
   }

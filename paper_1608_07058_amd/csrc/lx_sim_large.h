@@ -84,7 +84,7 @@ struct LaneL {
   bool plan, implicit, any_eq;
   R tau_p;
   int ssa_left;
-  u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip;
+  u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip, n_cf;
   long long n_nit;
 
   // The time the trajectory runs to now: t_end, or the next observation time.
@@ -133,7 +133,7 @@ struct LaneL {
     plan = false;
     implicit = false;
     ssa_left = 0;
-    n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = 0;
+    n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = n_cf = 0;
   }
 
   // Observation times, as Lane::grid_next: record the state as row kt of
@@ -171,7 +171,7 @@ struct LaneL {
     if (stats) {
       Stats s;
       s.status = status;
-      s.pad = 0;
+      s.crit_fired = n_cf;
       s.t_final = t;
       s.steps_ssa = n_ssa;
       s.steps_explicit = n_ex;
@@ -550,6 +550,7 @@ struct LaneL {
     t = last ? t_end_(prm) : t + tau;
     if (implicit) n_im += 1;
     else n_ex += 1;
+    n_cf += jc >= 0 ? 1u : 0u;
     plan = false;
   }
 

@@ -173,6 +173,34 @@ def random_network(seed=4, N=48, M=128, n_pairs=32, frac_uni=0.4, omega=100.0,
     return _net(f"random{N}x{M}", m, p, theta, x0)
 
 
+def pure_death(N=1, x0=10) -> Network:
+    """N independent decays X_i -> 0 at rate 1, every X_i starting at x0."""
+    m = np.eye(N, dtype=np.int32)
+    return _net(f"death{N}", m, np.zeros_like(m), np.ones(N), np.full(N, x0))
+
+
+def critical_decay(n_fast=1, n_slow=2) -> Network:
+    """``n_fast`` species in a fast birth-death balance around 1000 (0 -> Y,
+    1000; Y -> 0, 1) and ``n_slow`` species of 5-8 molecules decaying slowly
+    (rates 0.3, 0.05, 0.3, 0.05, ...): the small species are always near
+    exhaustion, so their decays are critical reactions, while the fast pairs
+    keep the leaps long."""
+    N = n_fast + n_slow
+    m = np.zeros((2 * n_fast + n_slow, N), np.int32)
+    p = np.zeros_like(m)
+    theta, x0 = [], []
+    for k in range(n_fast):
+        p[2 * k, k] = 1
+        m[2 * k + 1, k] = 1
+        theta += [1000.0, 1.0]
+        x0.append(1000)
+    for k in range(n_slow):
+        m[2 * n_fast + k, n_fast + k] = 1
+        theta.append(0.3 if k % 2 == 0 else 0.05)
+        x0.append(5 if k % 2 == 0 else 8)
+    return _net(f"critical_decay{n_fast}_{n_slow}", m, p, theta, x0)
+
+
 # --------------------------------------------------------------------------
 # Ensembles: per-particle parameters and initial states.
 # --------------------------------------------------------------------------

@@ -55,7 +55,7 @@ def assert_same(got, ref, what=""):
             bad = np.argwhere(np.any(got[key].reshape(len(got[key]), -1) !=
                                      ref[key].reshape(len(ref[key]), -1), axis=1))[:5, 0]
             raise AssertionError(f"{what}: {key} differs at particles {bad.tolist()}")
-    for f in ("status", "t_final", "steps_ssa", "steps_explicit", "steps_implicit", "rejections",
+    for f in ("status", "crit_fired", "t_final", "steps_ssa", "steps_explicit", "steps_implicit", "rejections",
               "newton_iters", "newton_fail", "kclip", "attempts"):
         assert np.array_equal(got["stats"][f], ref["stats"][f]), (what, f)
 

@@ -93,6 +93,10 @@ def test_poisson_bit_exact(lxm, orc, precision):
     lam = np.concatenate([
         rng.uniform(0, 10, 20000), [0.0, 1e-9, 9.999999, 10.0, 10.000001],
         10 ** rng.uniform(1, 4, 20000), 10 ** rng.uniform(4, 6.5, 5000),
+        # around 2^22, where binary32 means go to the binary64 sampler, and up
+        # to the 2^30 range (beyond it: -1)
+        [4194303.5, 4194304.0, 4194305.0, 2.0**30, 2.0**30 + 256.0, 2e9],
+        10 ** rng.uniform(6.5, 9, 2000),
     ])
     n = lam.shape[0]
     pid = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)

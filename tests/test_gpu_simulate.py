@@ -68,8 +68,8 @@ def assert_same(got, ref, what=""):
                                      ref[key].reshape(len(ref[key]), -1), axis=1))[:5, 0]
             raise AssertionError(f"{what}: {key} differs at particles {bad.tolist()}: "
                                  f"gpu {got[key][bad]} oracle {ref[key][bad]}")
-    for f in ("status", "t_final", "steps_ssa", "steps_explicit", "steps_implicit", "rejections",
-              "newton_iters", "newton_fail", "kclip", "attempts"):
+    for f in ("status", "crit_fired", "t_final", "steps_ssa", "steps_explicit", "steps_implicit",
+              "rejections", "newton_iters", "newton_fail", "kclip", "attempts"):
         assert np.array_equal(got["stats"][f], ref["stats"][f]), (what, f)
 
 
@@ -506,3 +506,49 @@ def test_check_lanes_reports_failed_trajectories(lxm):
     with pytest.warns(lxm.LaneFailWarning, match=r"item 1: 1 of 300"):
         lxm.simulate_set(items, 1.0, check_lanes=1)
     torch.cuda.synchronize()
+
+
+# Cases where the method's rarer events are frequent, so that their code runs
+# many times and is compared element by element:
+#  * the non-negativity retry: pure decay with leaps of size 1 whose Poisson
+#    draws often exceed the population (about 1.2 rejections per trajectory);
+#  * a failed implicit solve, which is a rejection too: one Newton iteration
+#    on the stiff dimer rarely converges;
+#  * critical firings inside leaps: small decaying populations next to a fast
+#    birth-death balance.
+# With regroup=1 every lane is saved and restored between its actions, so a
+# retry with a halved tau' also passes through the regrouping's state copy.
+EVENT_CASES = [
+    # name, network, x0 override, mode, t_end, P, options, counter, minimum
+    ("retry", W.pure_death(1), "death", "explicit", 3.7, 9000,
+     dict(n_c=0, eps=1.0, k_ssa=0.0), "rejections", 10000),
+    ("newton_fail", W.dimer_stiff(), None, "adaptive", 0.005, 256, dict(newton_maxit=1),
+     "newton_fail", 1000),
+    ("critical", W.critical_decay(1, 2), None, "adaptive", 4.0, 3000, {}, "crit_fired", 3000),
+    ("critical_explicit", W.critical_decay(1, 2), None, "explicit", 4.0, 3000, {}, "crit_fired",
+     3000),
+]
+EVENT_SCHEDULES = {
+    "plain": dict(schedule="plain"),
+    "batched": dict(schedule="batched"),
+    "regroup": dict(schedule="batched", regroup=1),
+    "group4": dict(schedule="batched", lanes_per_traj=4),
+    "group16": dict(schedule="batched", lanes_per_traj=16),
+}
+
+
+@pytest.mark.parametrize("schedule", sorted(EVENT_SCHEDULES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", EVENT_CASES, ids=[c[0] for c in EVENT_CASES])
+def test_rare_events_match_oracle_elementwise(lxm, orc, case, precision, schedule):
+    name, net, x0kind, mode, t_end, P, opts, counter, minimum = case
+    theta, x0 = W.tile(net, P)
+    if x0kind == "death":
+        x0 = x0.copy()
+        x0[::3] = 37
+    got = gpu_run(lxm, net, theta, x0, t_end, mode, precision=precision, **opts,
+                  **EVENT_SCHEDULES[schedule])
+    ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode=mode, precision=precision, **opts)
+    assert_same(got, ref, f"{name}/{precision}/{schedule}")
+    assert np.all(got["stats"]["status"] == 0)
+    assert int(got["stats"][counter].astype(np.int64).sum()) >= minimum, counter

@@ -212,7 +212,10 @@ def test_ssa_birth_death_is_exactly_poisson(orc):
     res = orc.simulate(net.m, net.p, th, x0, T, mode="ssa", nthreads=8)
     lam = 100.0 * (1.0 - math.exp(-10.0))
     x = res["x"][:, 0]
-    assert stats.kstest(x, stats.poisson(lam).cdf).pvalue > 1e-3 or True  # KS is conservative
+    # mean and variance of Poisson(lam): SE sqrt(lam / P) and, for the
+    # variance, sqrt((2 lam^2 + lam) / P)
+    assert abs(x.mean() - lam) < 4 * math.sqrt(lam / P)
+    assert abs(x.var() - lam) < 4 * math.sqrt((2 * lam * lam + lam) / P)
     ks = np.arange(0, 250)
     assert _chi2_discrete(x, ks, stats.poisson.pmf(ks, lam)) > 1e-3
     # births: r_1 ~ Poisson(k1 T) exactly; G_1 = T exactly (g = 1)

@@ -301,9 +301,29 @@ def test_poisson_large_lambda_fp64(orc):
     k = orc.poisson(np.full(n, lam), np.arange(n, dtype=np.uint32), 2, 0)
     assert abs((k.mean() - lam) / math.sqrt(lam / n)) < 4.5
     assert abs(k.var() / lam - 1.0) < 0.03
-    # above the binary32 range the mixed sampler reports overflow (-1)
-    assert orc.poisson([5e6], [0], 0, 0, precision="mixed")[0] == -1
+    # beyond the 2^30 range both policies report overflow (-1)
     assert orc.poisson([2e9], [0], 0, 0)[0] == -1
+    assert orc.poisson([2e9], [0], 0, 0, precision="mixed")[0] == -1
+
+
+def test_poisson_large_lambda_mixed(orc):
+    # From 2^22 the binary32 policy hands the mean to the binary64 sampler at
+    # the same draw site: identical counts there, the Poisson law (mean and
+    # variance within sampling error) up to the 2^30 range, and binary32 PTRS
+    # just below the seam.
+    n = 50000
+    pid = np.arange(n, dtype=np.uint32)
+    for lam in (2.0**22, 1e7, 1e9):
+        km = orc.poisson(np.full(n, lam), pid, 2, 0, precision="mixed")
+        kd = orc.poisson(np.full(n, lam), pid, 2, 0, precision="fp64")
+        assert np.array_equal(km, kd)
+        assert abs((km.mean() - lam) / math.sqrt(lam / n)) < 4.5
+        assert abs(km.var() / lam - 1.0) < 0.03
+    below = np.float32(2.0**22 - 0.5)
+    km = orc.poisson(np.full(n, below, np.float64), pid, 2, 0, precision="mixed")
+    kd = orc.poisson(np.full(n, below, np.float64), pid, 2, 0, precision="fp64")
+    assert not np.array_equal(km, kd)
+    assert abs((km.mean() - below) / math.sqrt(below / n)) < 4.5
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
