@@ -852,9 +852,8 @@ struct Traj {
     bool converged = false;
     for (int it = 0; it < o.newton_maxit; ++it) {
       st.newton_iters += 1;
-      // residual (g(y), products, sums) and Jacobian terms of the non-critical
-      // reactions: about 5 operations per (species, species, reaction) term
-      count_ops(net.g_cost + (uint64_t)M + 5 * (uint64_t)N + 5 * (uint64_t)N * N * M / 2);
+      // residual: g(y), products and sums
+      count_ops(net.g_cost + (uint64_t)M + 5 * (uint64_t)N);
       for (int j = 0; j < M; ++j) ay[j] = ncr[j] ? theta[j] * g_of(net, j, y.data()) : 0.0;
       for (int i = 0; i < N; ++i) {
         double s = 0.0;
@@ -867,6 +866,7 @@ struct Traj {
           double s = 0.0;
           for (int j = 0; j < M; ++j) {
             if (!ncr[j] || net.nu[j * N + i] == 0 || net.m[j * N + kk] == 0) continue;
+            count_ops(5);  // one Jacobian term: derivative, product, sum
             const double d = o.jacobian ? fd_dadk(j, kk, y, ay[j])
                                         : theta[j] * dg_of(net, j, kk, y.data());
             s = s + (double)net.nu[j * N + i] * d;

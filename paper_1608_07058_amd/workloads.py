@@ -16,6 +16,7 @@ its reversible pair so that implicit leaps occur.
 
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -106,18 +107,23 @@ def telegraph() -> Network:
                 ("on", "off", "transcribe", "mRNA decay", "translate", "protein decay"))
 
 
-def random_network(seed=4, N=48, M=128, n_pairs=32, frac_uni=0.4, omega=100.0,
-                   fast=(1.0, 1e2), slow=(1e-3, 1e-1)) -> Network:
+def random_network(seed=4, N=48, M=128, n_pairs=32, frac_uni=0.4, omega=100.0, n_fast=4,
+                   fast=(30.0, 1e2), slow=(1e-3, 1e-2)) -> Network:
     """Seeded random stiff mass-action network (large-network workload).
 
     N species, M reactions, 40 % unimolecular and 60 % bimolecular (2A
     allowed); products are 1-2 species with coefficients 1-2.  Species get
     masses w in {1, 2, 3}; every reaction satisfies w.p <= w.m, so the total
     mass never grows, and ``n_pairs`` reversible pairs conserve it exactly.
-    Stiffness: the pairs are fast (rate constants log-uniform on ``fast``),
-    the other reactions slow (log-uniform on ``slow``), all within
-    [1e-3, 1e2]; bimolecular constants are divided by the system size
-    ``omega``.  x0 is uniform on {50..500}.
+    x0 is uniform on {50..500}.
+
+    Rate constants (all within [1e-3, 1e2], bimolecular ones divided by the
+    system size ``omega``): the ``n_fast`` reversible pairs with the largest
+    flux at x0 (the smaller of the two directions' g) are fast, log-uniform
+    on ``fast``; every other reaction is slow, log-uniform on ``slow``.  After
+    a short relaxation the fast pairs sit in partial equilibrium and the
+    slow reactions bound the leap, so the ensemble runs implicit leaps with
+    a 48 x 48 Newton system.
     """
     rng = np.random.default_rng(seed)
     w = rng.integers(1, 4, size=N)
@@ -147,14 +153,14 @@ def random_network(seed=4, N=48, M=128, n_pairs=32, frac_uni=0.4, omega=100.0,
     kinds = np.array([0] * n_uni + [1] * (M - n_uni))
     rng.shuffle(kinds)
     rows = []
-    fast_rows = []
+    pairs = []
     # reversible pairs: the reverse reaction consumes exactly the products
-    while len(fast_rows) < 2 * n_pairs:
+    while len(pairs) < n_pairs:
         r = draw_reactants(bool(kinds[len(rows)]))
         q = draw_products(int(w @ r), exact=True)
         if q is None or np.array_equal(q, r) or q.sum() > 2:
             continue
-        fast_rows += [len(rows), len(rows) + 1]
+        pairs.append((len(rows), len(rows) + 1))
         rows += [(r, q), (q, r)]
     while len(rows) < M:
         r = draw_reactants(bool(kinds[len(rows)]))
@@ -164,12 +170,22 @@ def random_network(seed=4, N=48, M=128, n_pairs=32, frac_uni=0.4, omega=100.0,
         rows.append((r, q))
     for j, (r, q) in enumerate(rows):
         m[j], p[j] = r, q
-    theta = 10.0 ** rng.uniform(np.log10(slow[0]), np.log10(slow[1]), size=M)
-    fr = np.array(fast_rows)
-    theta[fr] = 10.0 ** rng.uniform(np.log10(fast[0]), np.log10(fast[1]), size=len(fr))
-    order = m.sum(axis=1)
-    theta = np.where(order >= 2, theta / omega, theta)
     x0 = rng.integers(50, 501, size=N)
+    order = m.sum(axis=1)
+
+    def g0(j):
+        out = 1.0
+        for i in np.nonzero(m[j])[0]:
+            out *= math.comb(int(x0[i]), int(m[j, i]))
+        return out / (omega if order[j] >= 2 else 1.0)
+
+    flux = np.array([min(g0(a), g0(b)) for a, b in pairs])
+    fast_pairs = set(np.argsort(-flux, kind="stable")[:n_fast].tolist())
+    theta = 10.0 ** rng.uniform(np.log10(slow[0]), np.log10(slow[1]), size=M)
+    for q, (a, b) in enumerate(pairs):
+        if q in fast_pairs:
+            theta[[a, b]] = 10.0 ** rng.uniform(np.log10(fast[0]), np.log10(fast[1]), size=2)
+    theta = np.where(order >= 2, theta / omega, theta)
     return _net(f"random{N}x{M}", m, p, theta, x0)
 
 
