@@ -73,6 +73,7 @@ typedef int32_t lx_status;
 /* Jacobian of the implicit solve (lx_options.jacobian). */
 #define LX_JAC_ANALYTIC 0
 #define LX_JAC_FD 1
+#define LX_JAC_USER 2 /* the derivative terms given to lx_network_create_jac */
 
 /* Per-trajectory status codes (lx_stats.status). */
 #define LX_LANE_OK 0
@@ -123,7 +124,8 @@ typedef struct lx_options {
                            the exact mass-action derivative, which is what a symbolic
                            Jacobian gives) or LX_JAC_FD (1, forward differences with the
                            step 2^-26 max(|y_k|, 1): the numerically estimated Jacobian
-                           (Background section) */
+                           (Background section), or LX_JAC_USER (2, the caller's symbolic
+                           derivative terms, lx_network_create_jac) */
   int32_t check_lanes;  /* 1: after launching, wait for the stream and read the status
                            of every trajectory from `stats` (which must then be
                            given); return LX_W_LANE_FAIL if any is not LX_LANE_OK,
@@ -173,6 +175,29 @@ const char* lx_last_error(void);
  * lx_network_destroy. */
 lx_status lx_network_create(int32_t N, int32_t M, const int32_t* reactant_order,
                             const int32_t* product_coeff, lx_network* out);
+
+/* lx_network_create with a caller-supplied Jacobian for the implicit solve
+ * (paper, Background section: the Jacobian of the implicit leap is
+ * estimated numerically unless a symbolic one is provided).  The caller gives
+ * d g_j / d y_k, for reactions j and their reactant species k, as polynomial
+ * terms: term t contributes coef[t] * prod_i y_i^powers[t][i] to
+ * d g_j / d y_k with (j, k) = (rxn[t], wrt[t]); the solve multiplies by
+ * theta_j.  Evaluation: per term, coef times repeated products in ascending
+ * species order; per (j, k), the terms summed from zero in table order; a
+ * reactant pair with no terms has derivative 0.  Simulations with
+ * opt->jacobian = LX_JAC_USER use these terms (the other choices stay
+ * available).
+ *   n_terms   1 .. 65536.
+ *   rxn, wrt  host int32 [n_terms]: reaction index in [0, M) and one of its
+ *             reactant species (m_kj > 0).
+ *   coef      host double [n_terms], finite.
+ *   powers    host int32 [n_terms][N], each in [0, 16].
+ * Arrays are read during the call only.  Errors: those of
+ * lx_network_create, and LX_E_INVALID for a term outside these rules. */
+lx_status lx_network_create_jac(int32_t N, int32_t M, const int32_t* reactant_order,
+                                const int32_t* product_coeff, int32_t n_terms,
+                                const int32_t* rxn, const int32_t* wrt, const double* coef,
+                                const int32_t* powers, lx_network* out);
 
 /* Compile (hipRTC, gfx950) and cache on disk the simulation kernel of a
  * network for a precision, schedule and block size (0 = default) without
@@ -291,8 +316,10 @@ typedef struct lx_pf_problem {
   double dt;            /* interval length > 0 */
   double obs_sd;        /* observation noise sd > 0 */
   const double* y;      /* [K] observations */
-  const double* alpha;  /* [M] prior shapes (>= 1: the Gamma sampler's range) */
-  const double* beta;   /* [M] prior rates (> 0) */
+  const double* alpha;  /* [M] prior shapes (> 0) */
+  const double* beta;   /* [M] prior rates (> 0; a shape or rate out of range makes the
+                           refreshed theta invalid and its particle ends the next
+                           interval with LX_LANE_BAD_INPUT, weight zero) */
   double* theta;        /* [P][M] in: initial parameters; out: last refresh */
   int32_t* x;           /* [P][N] in: initial states; out: states at K dt */
   int32_t* r;           /* [P][M] cumulative firing counts (normally zero at entry) */
@@ -310,6 +337,23 @@ lx_status lx_pf_workspace_size(int64_t P, int32_t N, int32_t M, size_t* bytes);
  * filter). */
 lx_status lx_pf_run(const lx_pf_problem* pb, double eps, int32_t mode, const lx_options* opt,
                     void* stream);
+
+/* lx_pf_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same filter, with pb->workspace and pb->workspace_bytes ignored in favour
+ * of a scratch array inside the library (64 MiB, a file-scope device array
+ * that each GPU the library runs on holds until the process ends; 2^18
+ * particles of a 4 x 6 network fit).  The call allocates nothing: it calls no
+ * hipMalloc/hipFree and loads no kernel.  Its first call on a device looks up
+ * the array's device address (which may load the library's own device code
+ * there).  Every call on a GPU shares that GPU's array, so calls that overlap
+ * on one GPU race; stream-ordered calls do not.  Errors: as lx_pf_run, and
+ * LX_E_INVALID when the filter needs more scratch than the array holds
+ * (lx_pf_workspace_size above 64 MiB) or when the simulation kernel for these
+ * options has not been loaded on this device yet (run the same filter once
+ * through lx_pf_run, which loads it). */
+lx_status lx_pf_run_static(const lx_pf_problem* pb, double eps, int32_t mode,
+                           const lx_options* opt, void* stream);
 
 /* A captured filter: all K intervals recorded once into a HIP graph on a
  * non-default `stream` (capture happens during the call; nothing executes),

@@ -41,6 +41,8 @@ class Options(C.Structure):
         ("newton_maxit", C.c_int32), ("rng_stream", C.c_uint32), ("pid_base", C.c_uint32),
         ("accumulate", C.c_int32), ("mode", C.c_int32), ("precision", C.c_int32),
         ("nthreads", C.c_int32), ("pid_stride", C.c_uint32), ("jacobian", C.c_int32),
+        ("n_jt", C.c_int32), ("jt_rxn", C.c_void_p), ("jt_wrt", C.c_void_p),
+        ("jt_coef", C.c_void_p), ("jt_pow", C.c_void_p),
     ]
 
 
@@ -112,10 +114,26 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
+JACOBIANS = {"analytic": 0, "fd": 1, "user": 2}
+
+
 def options(**kw) -> Options:
+    """Oracle options; ``jacobian_terms=(rxn, wrt, coef, powers)`` supplies
+    derivative terms (with ``jacobian="user"``), kept alive by the returned
+    object."""
     o = Options()
     lib().orc_default_options(C.byref(o))
+    terms = kw.pop("jacobian_terms", None)
+    if terms is not None:
+        rxn, wrt, coef, pw = terms
+        arrs = (np.ascontiguousarray(rxn, np.int32), np.ascontiguousarray(wrt, np.int32),
+                np.ascontiguousarray(coef, np.float64), np.ascontiguousarray(pw, np.int32))
+        o._keep = arrs
+        o.n_jt = len(arrs[0])
+        o.jt_rxn, o.jt_wrt, o.jt_coef, o.jt_pow = (a.ctypes.data for a in arrs)
     for k, v in kw.items():
+        if k == "jacobian" and isinstance(v, str):
+            v = JACOBIANS[v]
         if k == "mode" and isinstance(v, str):
             v = MODES[v]
         if k == "precision" and isinstance(v, str):

@@ -131,6 +131,10 @@ struct Rng {
 //   log: x = 2^e m with m in [sqrt(1/2), sqrt(2)), f = m - 1, s = f/(2+f),
 //        log(1+f) = f - f^2/2 + s (f^2/2 + R(s^2)), where R is the tail of the
 //        series 2 atanh(s) = 2s + 2s^3/3 + 2s^5/5 + ...; plus e ln2 in two parts.
+//        The reduction, the two-part ln 2 and the order in which the result
+//        is assembled follow the published fdlibm formulation of log
+//        (Sun Microsystems, e_log.c); the polynomial here is the Taylor tail
+//        of the atanh series, not fdlibm's minimax coefficients.
 // ---------------------------------------------------------------------------
 const double LN2_HI = 0x1.62e42feep-1;          // ln 2 truncated to 32 bits
 const double LN2_LO = 0x1.a39ef35793c76p-33;    // ln 2 - LN2_HI, rounded
@@ -595,7 +599,16 @@ typedef struct {
   uint32_t rng_stream, pid_base;
   int32_t accumulate, mode, precision, nthreads;
   uint32_t pid_stride;  // particle p uses id pid_base + p * pid_stride (0 means 1)
-  int32_t jacobian;     // 0: analytic mass-action Jacobian, 1: forward differences
+  int32_t jacobian;     // 0: analytic mass-action Jacobian, 1: forward differences,
+                        // 2: the caller's derivative terms below
+  // caller-supplied derivative terms (jacobian = 2): d g_j / d y_k is the sum,
+  // in table order, of coef[t] * prod_i y_i^pow[t][i] over the terms t with
+  // (jt_rxn[t], jt_wrt[t]) = (j, k)
+  int32_t n_jt;
+  const int32_t* jt_rxn;
+  const int32_t* jt_wrt;
+  const double* jt_coef;
+  const int32_t* jt_pow;  // [n_jt][N]
 } orc_options;
 
 typedef struct {
@@ -828,6 +841,22 @@ struct Traj {
     return (ayh - ayj) / h;
   }
 
+  // Caller-supplied derivative d g_j / d y_k (the symbolic Jacobian the
+  // paper allows in place of the numerical one, Background section): the
+  // terms of (j, k) in table order, each coef * prod_i y_i^pow_i by repeated
+  // products in ascending species order, summed from zero.
+  double dg_user(int j, int kk, const std::vector<double>& y) const {
+    double s = 0.0;
+    for (int t = 0; t < o.n_jt; ++t) {
+      if (o.jt_rxn[t] != j || o.jt_wrt[t] != kk) continue;
+      double v = o.jt_coef[t];
+      for (int i = 0; i < N; ++i)
+        for (int e = 0; e < o.jt_pow[(size_t)t * N + i]; ++e) v = v * y[i];
+      s = s + v;
+    }
+    return s;
+  }
+
   // Implicit tau-leap (Rathinam et al. 2003): solve for real y
   //   y = x + sum_{j noncritical} nu_j (tau a_j(y) - tau a_j(x) + P_j) + nu_jc [fired]
   // by Newton with the Jacobian I - tau sum_j nu_j grad a_j(y)^T, its entries
@@ -867,8 +896,10 @@ struct Traj {
           for (int j = 0; j < M; ++j) {
             if (!ncr[j] || net.nu[j * N + i] == 0 || net.m[j * N + kk] == 0) continue;
             count_ops(5);  // one Jacobian term: derivative, product, sum
-            const double d = o.jacobian ? fd_dadk(j, kk, y, ay[j])
-                                        : theta[j] * dg_of(net, j, kk, y.data());
+            double d;
+            if (o.jacobian == 1) d = fd_dadk(j, kk, y, ay[j]);
+            else if (o.jacobian == 2) d = theta[j] * dg_user(j, kk, y);
+            else d = theta[j] * dg_of(net, j, kk, y.data());
             s = s + (double)net.nu[j * N + i] * d;
           }
           J[i * N + kk] = (i == kk ? 1.0 : 0.0) - tau * s;
@@ -1113,7 +1144,7 @@ const double HALF_LOG_2PI_ = 0x1.d67f1c864beb5p-1;
 // Gamma(shape a >= 1, scale 1) by Marsaglia & Tsang (2000), with normal
 // variates from the polar method.  Trial t uses block 2t for the polar pair
 // and block 2t+1 for the acceptance uniform.
-double gamma_sample(double a, const Rng& rng, uint32_t e, uint32_t site) {
+double gamma_ge1(double a, const Rng& rng, uint32_t e, uint32_t site) {
   const double d = a - 1.0 / 3.0;
   const double c = 1.0 / std::sqrt(9.0 * d);
   uint32_t w[4];
@@ -1136,6 +1167,21 @@ double gamma_sample(double a, const Rng& rng, uint32_t e, uint32_t site) {
   return d;
 }
 
+// Gamma(shape a > 0, scale 1).  Below 1 by the boost of the same paper:
+// Gamma(a) = Gamma(a + 1) U^(1/a), with U the first uniform of block 128 of
+// the site (past the 128 blocks of the rounds above).  A shape that is not
+// positive and finite gives NaN.
+double gamma_sample(double a, const Rng& rng, uint32_t e, uint32_t site) {
+  if (!(a > 0.0) || a == std::numeric_limits<double>::infinity())
+    return std::numeric_limits<double>::quiet_NaN();
+  if (a >= 1.0) return gamma_ge1(a, rng, e, site);
+  const double y = gamma_ge1(a + 1.0, rng, e, site);
+  uint32_t w[4];
+  rng.block(e, site, 128, w);
+  const double u = uniform_f64(w[0], w[1]);
+  return y * exp_f64(log_f64(u) / a);
+}
+
 // floor(U64 * S / 2^64) for the resampling draw: an exact integer in [0, S).
 uint64_t scale_u64(uint64_t r, uint64_t S) {
   return (uint64_t)(((unsigned __int128)r * (unsigned __int128)S) >> 64);
@@ -1154,6 +1200,24 @@ void run_range(const Net& net, const orc_options& o, double t_end, int64_t lo, i
   }
 }
 
+// The Jacobian option and, for caller-supplied terms, the table: every term
+// names a reaction and one of its reactant species; powers are >= 0 and
+// coefficients finite.
+bool jacobian_ok(const Net& net, const orc_options& o) {
+  if (o.jacobian < 0 || o.jacobian > 2) return false;
+  if (o.jacobian != 2) return true;
+  if (o.n_jt < 1 || !o.jt_rxn || !o.jt_wrt || !o.jt_coef || !o.jt_pow) return false;
+  for (int t = 0; t < o.n_jt; ++t) {
+    const int j = o.jt_rxn[t], k = o.jt_wrt[t];
+    if (j < 0 || j >= net.M || k < 0 || k >= net.N || net.m[(size_t)j * net.N + k] == 0)
+      return false;
+    if (!std::isfinite(o.jt_coef[t])) return false;
+    for (int i = 0; i < net.N; ++i)
+      if (o.jt_pow[(size_t)t * net.N + i] < 0 || o.jt_pow[(size_t)t * net.N + i] > 16) return false;
+  }
+  return true;
+}
+
 int simulate_impl(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab, int64_t P,
                   const double* theta, const int32_t* x0, double t_end, const orc_options* opt,
                   int32_t* x_out, int32_t* r_out, double* G_out, orc_stats* stats, int K,
@@ -1162,7 +1226,8 @@ int simulate_impl(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab
   if (build_net(N, M, mtab, ptab, &net) != 0) return -1;
   const orc_options& o = *opt;
   if (!(o.lambda_thr >= 1.0 && o.lambda_thr <= 30.0) || o.n_c < 0 || o.mode < 0 || o.mode > 2 ||
-      !(t_end >= o.t_start) || !(o.eps > 0.0) || o.precision < 0 || o.precision > 1)
+      !(t_end >= o.t_start) || !(o.eps > 0.0) || o.precision < 0 || o.precision > 1 ||
+      !jacobian_ok(net, o))
     return -2;
   int nth = o.nthreads > 0 ? o.nthreads : (int)std::max(1u, std::thread::hardware_concurrency());
   nth = (int)std::min<int64_t>(nth, std::max<int64_t>(P, 1));
@@ -1375,6 +1440,7 @@ int orc_implicit(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab,
                  int32_t* ok, int32_t* iters) {
   Net net;
   if (build_net(N, M, mtab, ptab, &net) != 0) return -1;
+  if (!jacobian_ok(net, *opt)) return -2;
   for (int64_t q = 0; q < Q; ++q) {
     Traj<PolicyF64> tr(net, *opt, 1.0);
     for (int j = 0; j < M; ++j) { tr.theta[j] = theta[q * M + j]; tr.theta_r[j] = theta[q * M + j]; }

@@ -50,6 +50,7 @@ hipError_t lxh_launch_gamma(long long, const double*, const unsigned*, const uns
 
 // Particle-filter kernels (lx_pf.hip).
 size_t lxpf_workspace_layout(long long P, int N, int M, char* base, lx::PfWork* w);
+hipError_t lxpf_static_scratch(void** ptr, size_t* bytes);
 hipError_t lxpf_launch_interval(long long P, int N, int M, int* x, int* r, double* G,
                                 double* theta, const double* y_k, int obs, double sd,
                                 const double* alpha, const double* beta, unsigned k0,
@@ -177,6 +178,9 @@ struct lx_network_s {
   int N = 0, M = 0, npairs = 0;
   bool large = false;  // beyond the register-resident limits: lx_sim_large.h kernels
   std::vector<int> ro, nu, phi, partner;
+  // caller-supplied derivative terms (lx_network_create_jac), in table order
+  std::vector<int> jt_rxn, jt_wrt, jt_pow;  // jt_pow [n][N]
+  std::vector<double> jt_coef;
   std::string netsrc;
   std::mutex mu;
   std::map<std::string, Kernel> kernels;  // variant key -> loaded kernel
@@ -206,6 +210,64 @@ std::string vec_src(const char* name, const std::vector<int>& v) {
   s << "  static constexpr int " << name << "[" << v.size() << "] = {";
   for (size_t q = 0; q < v.size(); ++q) s << (q ? "," : "") << v[q];
   s << "};\n";
+  return s.str();
+}
+
+std::string dvec_src(const char* name, const std::vector<double>& v) {
+  std::ostringstream s;
+  s << "  static constexpr double " << name << "[" << v.size() << "] = {";
+  for (size_t q = 0; q < v.size(); ++q) {
+    char buf[40];
+    snprintf(buf, sizeof(buf), "%a", v[q]);
+    s << (q ? "," : "") << buf;
+  }
+  s << "};\n";
+  return s.str();
+}
+
+// Caller-supplied derivative terms of d g_j / d y_k as compile-time tables:
+// term t has reaction JT_J[t], species JT_K[t], coefficient JT_C[t] and the
+// factors y_{JT_SP[f]}^{JT_PW[f]}, f in [JT_PTR[t], JT_PTR[t+1]), in
+// ascending species order; JT_SLOT_PTR / JT_SLOT_T list, for every reactant
+// slot q of RX_PTR order (reaction j, its q-th reactant species), the terms
+// of that (j, k) in table order.  Empty tables hold one unused entry.
+std::string jacobian_src(const lx_network_s& n) {
+  const int T = (int)n.jt_rxn.size();
+  std::vector<int> J(n.jt_rxn), K(n.jt_wrt), ptr(1, 0), sp, pw;
+  std::vector<double> C(n.jt_coef);
+  for (int t = 0; t < T; ++t) {
+    for (int i = 0; i < n.N; ++i) {
+      const int e = n.jt_pow[(size_t)t * n.N + i];
+      if (e) {
+        sp.push_back(i);
+        pw.push_back(e);
+      }
+    }
+    ptr.push_back((int)sp.size());
+  }
+  std::vector<int> slot_ptr(1, 0), slot_t;
+  for (int j = 0; j < n.M; ++j)
+    for (int i = 0; i < n.N; ++i) {
+      if (n.ro[(size_t)j * n.N + i] == 0) continue;
+      for (int t = 0; t < T; ++t)
+        if (J[t] == j && K[t] == i) slot_t.push_back(t);
+      slot_ptr.push_back((int)slot_t.size());
+    }
+  if (T == 0) {
+    J.assign(1, -1);
+    K.assign(1, -1);
+    C.assign(1, 0.0);
+  }
+  if (sp.empty()) {
+    sp.push_back(0);
+    pw.push_back(0);
+  }
+  if (slot_t.empty()) slot_t.push_back(0);
+  std::ostringstream s;
+  s << "  static constexpr int NJT = " << T << ";\n";
+  s << vec_src("JT_J", J) << vec_src("JT_K", K) << dvec_src("JT_C", C) << vec_src("JT_PTR", ptr)
+    << vec_src("JT_SP", sp) << vec_src("JT_PW", pw) << vec_src("JT_SLOT_PTR", slot_ptr)
+    << vec_src("JT_SLOT_T", slot_t);
   return s.str();
 }
 
@@ -246,6 +308,7 @@ std::string network_source(const lx_network_s& n) {
     csr_src(s, "NI_PTR", "NI_RX", "NI_V", n.nu, n.N, n.M, true, false);
     s << vec_src("PHI", n.phi);
     s << vec_src("PARTNER", n.partner);
+    s << jacobian_src(n);
     s << "};\n";
     return s.str();
   }
@@ -255,6 +318,7 @@ std::string network_source(const lx_network_s& n) {
   s << table_src("NU", n.nu, n.M, n.N);
   s << vec_src("PHI", n.phi);
   s << vec_src("PARTNER", n.partner);
+  s << jacobian_src(n);
   s << "};\n";
   return s.str();
 }
@@ -359,7 +423,7 @@ lx_status check_device(int* dev_out) {
 // from the cache of network `owner`; `make_src` produces its source.
 template <class F>
 lx_status get_kernel_src(lx_network_s* owner, const std::string& variant_key, F make_src,
-                         const char* fname, hipFunction_t* fn) {
+                         const char* fname, hipFunction_t* fn, bool may_load = true) {
   int dev = 0;
   lx_status st = check_device(&dev);
   if (st != LX_OK) return st;
@@ -371,6 +435,11 @@ lx_status get_kernel_src(lx_network_s* owner, const std::string& variant_key, F 
     *fn = it->second.fn;
     return LX_OK;
   }
+  if (!may_load)
+    return fail(LX_E_INVALID,
+                "the simulation kernel for these options is not loaded on this device yet "
+                "(loading allocates device memory): run the same call once through the "
+                "allocating entry point first");
   std::vector<char> code;
   st = compile_source(make_src(), &code);
   if (st != LX_OK) return st;
@@ -391,14 +460,14 @@ lx_status get_kernel_src(lx_network_s* owner, const std::string& variant_key, F 
 // "large" or "hooks", precision LX_PREC_*, `grid` for observation times.
 lx_status get_kernel(lx_network_s* net, const char* variant, int precision, int block,
                      const char* fname, hipFunction_t* fn, int tpl, const std::string& consts,
-                     bool grid = false) {
+                     bool grid = false, bool may_load = true) {
   std::ostringstream key;
   key << variant << (grid ? "-grid" : "") << "/" << precision << "/" << block << "/tpl" << tpl
       << "/c" << std::hex << fnv1a(consts) << std::dec;
   return get_kernel_src(
       net, key.str(),
       [&]() { return kernel_source(*net, variant, precision, block, tpl, consts, grid); }, fname,
-      fn);
+      fn, may_load);
 }
 
 // Schedule-dependent fields of the launch parameters in canonical form (they
@@ -464,8 +533,8 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
     return fail(LX_E_INVALID, "lanes_per_wave must be at least lanes_per_traj");
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 8)
     return fail(LX_E_INVALID, "blocks_per_cu must be in [0, 8]");
-  if (o.jacobian != LX_JAC_ANALYTIC && o.jacobian != LX_JAC_FD)
-    return fail(LX_E_INVALID, "jacobian must be LX_JAC_ANALYTIC or LX_JAC_FD");
+  if (o.jacobian != LX_JAC_ANALYTIC && o.jacobian != LX_JAC_FD && o.jacobian != LX_JAC_USER)
+    return fail(LX_E_INVALID, "jacobian must be LX_JAC_ANALYTIC, LX_JAC_FD or LX_JAC_USER");
   {
     const uint64_t stride = o.pid_stride ? o.pid_stride : 1;
     if (P > 0 && (uint64_t)o.pid_base + (uint64_t)(P - 1) * stride >= 4294967296ull)
@@ -536,9 +605,12 @@ struct SimLaunch {
 };
 
 lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end, double eps,
-                   int32_t mode, SimLaunch* L, bool grid = false) {
+                   int32_t mode, SimLaunch* L, bool grid = false, bool may_load = true) {
   lx_status st = fill_params(o, P, t_end, eps, mode, &L->prm);
   if (st != LX_OK) return st;
+  if (o.jacobian == LX_JAC_USER && net->jt_rxn.empty())
+    return fail(LX_E_INVALID, "LX_JAC_USER needs a network created with derivative terms "
+                              "(lx_network_create_jac)");
   if (P == 0) return LX_OK;
   if (net->large) {
     // One lane per trajectory; the plain schedule gives every lane one
@@ -552,7 +624,7 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
     L->block = o.block_size ? o.block_size : (batched ? 256 : 64);
     finish_params(o, true, &L->prm);
     st = get_kernel(net, "large", o.precision, L->block, "lx_sim_large", &L->fn, 1,
-                    const_source(L->prm), grid);
+                    const_source(L->prm), grid, may_load);
     if (st != LX_OK) return st;
     long long per_block = L->block;
     int lanes = 64;
@@ -577,7 +649,7 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
   finish_params(o, L->batched, &L->prm);
   st = get_kernel(net, L->batched ? "batched" : "plain", o.precision, L->block,
                   L->batched ? "lx_sim_batched" : "lx_sim_plain", &L->fn,
-                  L->batched ? tpl_of(o) : 1, const_source(L->prm), grid);
+                  L->batched ? tpl_of(o) : 1, const_source(L->prm), grid, may_load);
   if (st != LX_OK) return st;
   L->grid = (P + L->block - 1) / L->block;
   if (L->batched) {
@@ -707,6 +779,38 @@ lx_status lx_network_create(int32_t N, int32_t M, const int32_t* ro, const int32
       }
     }
   }
+  n->netsrc = network_source(*n);
+  *out = n;
+  return LX_OK;
+}
+
+lx_status lx_network_create_jac(int32_t N, int32_t M, const int32_t* reactant_order,
+                                const int32_t* product_coeff, int32_t n_terms,
+                                const int32_t* rxn, const int32_t* wrt, const double* coef,
+                                const int32_t* powers, lx_network* out) {
+  if (!out) return fail(LX_E_INVALID, "out is null");
+  *out = nullptr;
+  if (n_terms < 1 || n_terms > 65536 || !rxn || !wrt || !coef || !powers)
+    return fail(LX_E_INVALID, "need 1 to 65536 derivative terms and non-null term arrays");
+  lx_network n = nullptr;
+  lx_status st = lx_network_create(N, M, reactant_order, product_coeff, &n);
+  if (st != LX_OK) return st;
+  for (int t = 0; t < n_terms; ++t) {
+    const int j = rxn[t], k = wrt[t];
+    bool ok = j >= 0 && j < M && k >= 0 && k < N && n->ro[(size_t)j * N + k] > 0 &&
+              std::isfinite(coef[t]);
+    for (int i = 0; i < N && ok; ++i) ok = powers[(size_t)t * N + i] >= 0 && powers[(size_t)t * N + i] <= 16;
+    if (!ok) {
+      delete n;
+      return fail(LX_E_INVALID, "derivative term " + std::to_string(t) +
+                                    ": it must name a reaction and one of its reactant species, "
+                                    "with a finite coefficient and powers in [0, 16]");
+    }
+  }
+  n->jt_rxn.assign(rxn, rxn + n_terms);
+  n->jt_wrt.assign(wrt, wrt + n_terms);
+  n->jt_coef.assign(coef, coef + n_terms);
+  n->jt_pow.assign(powers, powers + (size_t)n_terms * N);
   n->netsrc = network_source(*n);
   *out = n;
   return LX_OK;
@@ -1019,7 +1123,7 @@ lx_status lx_pf_workspace_size(int64_t P, int32_t N, int32_t M, size_t* bytes) {
 namespace {
 
 lx_status pf_check(const lx_pf_problem* pb, double eps, int32_t mode, const lx_options* opt,
-                   lx_options* o, SimLaunch* L, lx::PfWork* w) {
+                   lx_options* o, SimLaunch* L, lx::PfWork* w, bool may_load = true) {
   if (!pb || !pb->net) return fail(LX_E_INVALID, "null problem or network");
   const lx_pf_problem& q = *pb;
   if (q.net->large)
@@ -1039,7 +1143,7 @@ lx_status pf_check(const lx_pf_problem* pb, double eps, int32_t mode, const lx_o
   o->pid_base = 0;
   o->pid_stride = 1;
   o->t_start = 0.0;
-  lx_status st = plan_sim(q.net, q.P, *o, q.dt, eps, mode, L);
+  lx_status st = plan_sim(q.net, q.P, *o, q.dt, eps, mode, L, false, may_load);
   if (st != LX_OK) return st;
   lxpf_workspace_layout(q.P, q.net->N, q.net->M, (char*)q.workspace, w);
   return LX_OK;
@@ -1081,6 +1185,31 @@ lx_status lx_pf_run(const lx_pf_problem* pb, double eps, int32_t mode, const lx_
   lx_status st = pf_check(pb, eps, mode, opt, &o, &L, &w);
   if (st != LX_OK) return st;
   return pf_enqueue(*pb, o, L, w, (hipStream_t)stream);
+}
+
+lx_status lx_pf_run_static(const lx_pf_problem* pb, double eps, int32_t mode,
+                           const lx_options* opt, void* stream) {
+  if (!pb || !pb->net) return fail(LX_E_INVALID, "null problem or network");
+  void* base = nullptr;
+  size_t bytes = 0;
+  hipError_t e = lxpf_static_scratch(&base, &bytes);
+  if (e != hipSuccess) return hip_fail(e, "address of the filter's static scratch");
+  if (pb->P >= 1 && pb->net->N >= 1 && pb->net->M >= 1 && pb->P <= (1LL << 23)) {
+    const size_t need = lxpf_workspace_layout(pb->P, pb->net->N, pb->net->M, nullptr, nullptr);
+    if (need > bytes)
+      return fail(LX_E_INVALID, "lx_pf_run_static: the filter needs " + std::to_string(need) +
+                                    " bytes of scratch, above its static maximum of " +
+                                    std::to_string(bytes) + " (use lx_pf_run with a workspace)");
+  }
+  lx_pf_problem q = *pb;
+  q.workspace = base;
+  q.workspace_bytes = bytes;
+  lx_options o;
+  SimLaunch L;
+  lx::PfWork w;
+  lx_status st = pf_check(&q, eps, mode, opt, &o, &L, &w, false);
+  if (st != LX_OK) return st;
+  return pf_enqueue(q, o, L, w, (hipStream_t)stream);
 }
 
 lx_status lx_pf_graph_create(const lx_pf_problem* pb, double eps, int32_t mode,

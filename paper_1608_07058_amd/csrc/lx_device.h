@@ -77,7 +77,9 @@ __device__ __forceinline__ double uniform_f64(u32 hi, u32 lo) {
 //        e^r by its Taylor polynomial in Horner form, times 2^k.
 //   log: x = 2^e m, m in [sqrt(1/2), sqrt(2)), f = m - 1, s = f / (2 + f);
 //        log(1 + f) = f - f^2/2 + s (f^2/2 + R(s^2)) with R the tail of the
-//        atanh series, plus e ln2 in two parts.
+//        atanh series, plus e ln2 in two parts (reduction and assembly as in
+//        the published fdlibm log, e_log.c; the polynomial is the Taylor tail
+//        of the atanh series, not fdlibm's minimax coefficients).
 // ---------------------------------------------------------------------------
 // Each function is a core for ordinary arguments (exp: within the overflow
 // and underflow limits; log: positive and finite) and a wrapper that answers
@@ -410,6 +412,12 @@ __device__ __forceinline__ long long poisson_ptrs(typename P::R lam, const Key& 
   return (long long)__builtin_floor((double)lam);
 }
 
+// The binary64 PTRS draw of a binary32 mean at or beyond 2^22, out of line: a
+// rare path, kept out of the callers' code and registers.
+__device__ __noinline__ long long poisson_wide(double lam, Key key, u32 pid, u32 e, u32 site) {
+  return poisson_ptrs<F64>(lam, key, pid, e, site);
+}
+
 // Inversion below the PTRS threshold (sequential search of the CDF).
 template <class P>
 __device__ __forceinline__ long long poisson_inversion(typename P::R lam, int kcap, const Key& key,
@@ -439,7 +447,7 @@ __device__ __forceinline__ long long poisson_sample(typename P::R lam, typename 
   if (!(lam > (R)0)) return 0;
   if ((double)lam > P::lambda_max()) return -1;
   if constexpr (P::mixed) {
-    if ((double)lam >= P::wide_from()) return poisson_ptrs<F64>((double)lam, key, pid, e, site);
+    if ((double)lam >= P::wide_from()) return poisson_wide((double)lam, key, pid, e, site);
   }
   if (lam < lam_thr) return poisson_inversion<P>(lam, kcap, key, pid, e, site);
   return poisson_ptrs<P>(lam, key, pid, e, site);
@@ -455,14 +463,16 @@ __device__ __noinline__ long long poisson_sample_call(typename P::R lam, typenam
 }
 
 // ---------------------------------------------------------------------------
-// Gamma(a >= 1, scale 1): Marsaglia & Tsang (2000) with normal variates from
-// the polar method.  Trial t draws block 2t for the polar pair and block 2t+1
-// for the acceptance uniform.
+// Gamma(a > 0, scale 1): Marsaglia & Tsang (2000) with normal variates from
+// the polar method for a >= 1.  Trial t draws block 2t for the polar pair and
+// block 2t+1 for the acceptance uniform.  Below 1 their boost:
+// Gamma(a) = Gamma(a + 1) U^(1/a), U the first uniform of block 128.  A shape
+// that is not positive and finite gives NaN.
 // ---------------------------------------------------------------------------
 constexpr u32 SITE_RESAMPLE = 0x40000002u;
 constexpr u32 SITE_GAMMA = 0x40000010u;  // + reaction index
 
-__device__ __noinline__ double gamma_sample(double a, const Key& key, u32 pid, u32 e, u32 site) {
+__device__ __forceinline__ double gamma_ge1(double a, const Key& key, u32 pid, u32 e, u32 site) {
   const double d = a - 1.0 / 3.0;
   const double c = 1.0 / __builtin_sqrt(9.0 * d);
   for (u32 t = 0; t < 64; ++t) {
@@ -482,6 +492,16 @@ __device__ __noinline__ double gamma_sample(double a, const Key& key, u32 pid, u
     if (log_f64(u) < (((0.5 * zz) + d) - d * v) + d * log_f64(v)) return d * v;
   }
   return d;
+}
+
+__device__ __noinline__ double gamma_sample(double a, const Key& key, u32 pid, u32 e, u32 site) {
+  if (!(a > 0.0) || a == LX_INF_F64) return __builtin_nan("");
+  const bool boost = a < 1.0;
+  const double y = gamma_ge1(boost ? a + 1.0 : a, key, pid, e, site);
+  if (!boost) return y;
+  const Words4 w = draw_block(key, pid, e, site, 128);
+  const double u = uniform_f64(w.w0, w.w1);
+  return y * exp_f64(log_f64(u) / a);
 }
 
 }  // namespace lx

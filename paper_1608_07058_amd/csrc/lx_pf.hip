@@ -15,6 +15,8 @@
 //   5. copy back and the interval's log-likelihood increment.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "lx_device.h"
 #include "lx_params.h"
 
@@ -219,4 +221,38 @@ hipError_t lxpf_launch_interval(long long P, int N, int M, int* x, int* r, doubl
   hipLaunchKernelGGL(lxpf::copyback_kernel, g, b, 0, s, P, N, M, w.x2, w.r2, w.G2, x, r, G, w.mx,
                      w.total, ll_k);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of lx_pf_run_static, the filter entry point for callers that cannot
+// allocate device memory: a file-scope device array that each GPU holds for
+// the life of the process.  Host code never passes `scratch` itself (on the
+// host the name is only a stand-in): it passes the device address looked up
+// here once per device, with that device current.  Every piece of the
+// workspace carved from it is written before it is read within each
+// interval, so nothing needs clearing; calls that overlap on one GPU share
+// the array and race.
+// ---------------------------------------------------------------------------
+constexpr size_t LXPF_STATIC_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[LXPF_STATIC_BYTES];
+
+constexpr int LXPF_MAX_DEVICES = 64;
+
+hipError_t lxpf_static_scratch(void** ptr, size_t* bytes) {
+  static std::mutex mu;
+  static void* addr[LXPF_MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= LXPF_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = a;
+  }
+  *ptr = addr[dev];
+  *bytes = LXPF_STATIC_BYTES;
+  return hipSuccess;
 }

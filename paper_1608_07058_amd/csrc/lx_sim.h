@@ -80,6 +80,26 @@ __device__ __forceinline__ double dg_of(int j, int k, const double (&y)[NET::N])
   return gj;
 }
 
+// d g_j / d y_k from the caller's derivative terms of (j, k) (NET::JT_*):
+// each term its coefficient times repeated products of y in ascending species
+// order, summed from zero in table order.  j and k are compile-time after
+// unrolling, so only that pair's terms remain.
+template <class NET>
+__device__ __forceinline__ double dg_user(int j, int k, const double (&y)[NET::N]) {
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < NET::NJT; ++t) {
+    if (NET::JT_J[t] != j || NET::JT_K[t] != k) continue;
+    double v = NET::JT_C[t];
+#pragma unroll
+    for (int f = NET::JT_PTR[t]; f < NET::JT_PTR[t + 1]; ++f)
+#pragma unroll
+      for (int e = 0; e < NET::JT_PW[f]; ++e) v = v * y[NET::JT_SP[f]];
+    s = s + v;
+  }
+  return s;
+}
+
 // Cross-lane read within groups of TPL lanes (lane s of the caller's group).
 // Groups of 2 and 4 lanes lie within a quad of the wave, so the read is a
 // DPP quad permutation (a VALU move, no LDS round trip); a group of 16 is a
@@ -668,10 +688,10 @@ struct Lane {
           if (NET::NU[j][i] != 0 && ((ncr >> j) & 1u)) s = s + (double)NET::NU[j][i] * ay[j];
         b[i] = -((y[i] - c[i]) - tau * s);
       }
-      // d a_j / d y_k: analytic, or forward differences (a_j re-evaluated with
-      // y_k moved by the representable step h_k)
+      // d a_j / d y_k: analytic, forward differences (a_j re-evaluated with
+      // y_k moved by the representable step h_k), or the caller's terms
       double yh[N], h[N];
-      if (LXP(prm, jacobian)) {
+      if (LXP(prm, jacobian) == 1) {
 #pragma unroll
         for (int kk = 0; kk < N; ++kk) h[kk] = fd_step(y[kk], &yh[kk]);
       }
@@ -684,9 +704,11 @@ struct Lane {
           for (int j = 0; j < M; ++j) {
             if (NET::NU[j][i] == 0 || NET::RO[j][kk] == 0) continue;
             if ((ncr >> j) & 1u) {
-              const double d = LXP(prm, jacobian)
-                                   ? (th[j] * g_moved<NET>(j, kk, y, yh[kk]) - ay[j]) / h[kk]
-                                   : th[j] * dg_of<NET>(j, kk, y);
+              const double d =
+                  LXP(prm, jacobian) == 1
+                      ? (th[j] * g_moved<NET>(j, kk, y, yh[kk]) - ay[j]) / h[kk]
+                      : (LXP(prm, jacobian) == 2 ? th[j] * dg_user<NET>(j, kk, y)
+                                                 : th[j] * dg_of<NET>(j, kk, y));
               s = s + (double)NET::NU[j][i] * d;
             }
           }

@@ -56,6 +56,21 @@ __device__ __forceinline__ double dg_large(int j, int k, const double* y) {
   return gj;
 }
 
+// d g_j / d y_k from the caller's terms of reactant slot q (reaction j, its
+// species k): JT_SLOT_T lists them in table order (as dg_user).
+template <class NET>
+__device__ __forceinline__ double dg_user_large(int q, const double* y) {
+  double s = 0.0;
+  for (int u = NET::JT_SLOT_PTR[q]; u < NET::JT_SLOT_PTR[q + 1]; ++u) {
+    const int t = NET::JT_SLOT_T[u];
+    double v = NET::JT_C[t];
+    for (int f = NET::JT_PTR[t]; f < NET::JT_PTR[t + 1]; ++f)
+      for (int e = 0; e < NET::JT_PW[f]; ++e) v = v * y[NET::JT_SP[f]];
+    s = s + v;
+  }
+  return s;
+}
+
 template <class P, class NET, bool GRID = false>
 struct LaneL {
   typedef typename P::R R;
@@ -397,7 +412,9 @@ struct LaneL {
         for (int qk = NET::RX_PTR[j]; qk < NET::RX_PTR[j + 1]; ++qk) {
           const int kk = NET::RX_SP[qk];
           double d;
-          if (LXP(prm, jacobian)) {  // forward difference, as Lane::implicit_counts
+          if (LXP(prm, jacobian) == 2) {  // the caller's derivative terms
+            d = th[j] * dg_user_large<NET>(qk, y);
+          } else if (LXP(prm, jacobian) == 1) {  // forward difference, as Lane::implicit_counts
             const double yk = y[kk];
             double yh;
             const double hk = fd_step(yk, &yh);

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblx.so")
 
 MODES = {"adaptive": 0, "explicit": 1, "ssa": 2}
+JACOBIANS = {"analytic": 0, "fd": 1, "user": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 SCHEDULES = {"plain": 0, "batched": 1}
 LANE_STATUS = {0: "OK", 1: "STEP_BUDGET", 2: "LAMBDA_OVERFLOW", 3: "BAD_INPUT",
@@ -28,7 +29,8 @@ EXPORTS = (
     "lx_test_uniform_f64", "lx_test_uniform_f32", "lx_test_math", "lx_test_poisson",
     "lx_test_exponential", "lx_test_tau_select", "lx_test_implicit", "lx_simulate_set",
     "lx_pf_workspace_size", "lx_pf_run", "lx_pf_graph_create", "lx_pf_graph_launch",
-    "lx_pf_graph_destroy", "lx_test_gamma", "lx_simulate_grid",
+    "lx_pf_graph_destroy", "lx_test_gamma", "lx_simulate_grid", "lx_pf_run_static",
+    "lx_network_create_jac",
 )
 
 
@@ -97,6 +99,8 @@ def lib():
         L.lx_options_default.restype = None
         L.lx_last_error.restype = C.c_char_p
         L.lx_network_create.argtypes = [I32, I32, P, P, C.POINTER(C.c_void_p)]
+        L.lx_network_create_jac.argtypes = [I32, I32, P, P, I32, P, P, P, P,
+                                            C.POINTER(C.c_void_p)]
         L.lx_network_prepare.argtypes = [P, I32, I32, I32]
         L.lx_network_destroy.argtypes = [P]
         L.lx_network_info.argtypes = [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]
@@ -106,6 +110,7 @@ def lib():
         L.lx_simulate_set.argtypes = [I32, C.POINTER(SetItem), D, D, I32, C.POINTER(Options), P]
         L.lx_pf_workspace_size.argtypes = [I64, I32, I32, C.POINTER(C.c_size_t)]
         L.lx_pf_run.argtypes = [C.POINTER(PfProblem), D, I32, C.POINTER(Options), P]
+        L.lx_pf_run_static.argtypes = [C.POINTER(PfProblem), D, I32, C.POINTER(Options), P]
         L.lx_pf_graph_create.argtypes = [C.POINTER(PfProblem), D, I32, C.POINTER(Options), P,
                                          C.POINTER(C.c_void_p)]
         L.lx_pf_graph_launch.argtypes = [P, P]
@@ -154,6 +159,8 @@ def options(**kw) -> Options:
             v = PRECISIONS[v]
         if k == "schedule" and isinstance(v, str):
             v = SCHEDULES[v]
+        if k == "jacobian" and isinstance(v, str):
+            v = JACOBIANS[v]
         if k not in dict(Options._fields_):
             raise KeyError(f"unknown option {k!r}")
         setattr(o, k, v)
@@ -163,15 +170,28 @@ def options(**kw) -> Options:
 class Network:
     """A compiled reaction network (lx_network_create)."""
 
-    def __init__(self, reactant_order, product_coeff):
+    def __init__(self, reactant_order, product_coeff, jacobian_terms=None):
+        """``jacobian_terms=(rxn, wrt, coef, powers)``: derivative terms for
+        jacobian="user" (lx_network_create_jac)."""
         m = np.ascontiguousarray(reactant_order, dtype=np.int32)
         p = np.ascontiguousarray(product_coeff, dtype=np.int32)
         if m.ndim != 2 or m.shape != p.shape:
             raise ValueError("reactant/product tables must both be [M][N]")
         self.M, self.N = m.shape
         h = C.c_void_p()
-        _check(lib().lx_network_create(self.N, self.M, m.ctypes.data, p.ctypes.data, C.byref(h)),
-               "lx_network_create")
+        if jacobian_terms is None:
+            _check(lib().lx_network_create(self.N, self.M, m.ctypes.data, p.ctypes.data,
+                                           C.byref(h)), "lx_network_create")
+        else:
+            rxn, wrt, coef, pw = jacobian_terms
+            rxn = np.ascontiguousarray(rxn, np.int32)
+            wrt = np.ascontiguousarray(wrt, np.int32)
+            coef = np.ascontiguousarray(coef, np.float64)
+            pw = np.ascontiguousarray(pw, np.int32).reshape(len(rxn), self.N)
+            _check(lib().lx_network_create_jac(self.N, self.M, m.ctypes.data, p.ctypes.data,
+                                               len(rxn), rxn.ctypes.data, wrt.ctypes.data,
+                                               coef.ctypes.data, pw.ctypes.data, C.byref(h)),
+                   "lx_network_create_jac")
         self._h = h
 
     @property
@@ -329,13 +349,15 @@ class ParticleFilter:
     """lx_pf_*: particle filter over K observation intervals on device tensors.
 
     theta [P][M] f64, x [P][N] i32 (updated in place), y [K], alpha/beta [M].
-    Allocates r, G, loglik and the workspace with torch.  ``run()`` enqueues
-    direct launches; ``capture(stream)`` records a HIP graph once and
-    ``replay(stream)`` launches it.
+    Allocates r, G, loglik and (unless ``workspace=False``) the workspace with
+    torch.  ``run()`` enqueues direct launches; ``capture(stream)`` records a
+    HIP graph once and ``replay(stream)`` launches it; ``run_static()`` is
+    lx_pf_run_static, which uses the library's own scratch instead of the
+    workspace.
     """
 
     def __init__(self, net, theta, x, y, alpha, beta, dt, obs_species, obs_sd, eps=0.03,
-                 mode="adaptive", **opts):
+                 mode="adaptive", workspace=True, **opts):
         import torch
         self.net = net
         P, K = theta.shape[0], y.shape[0]
@@ -349,9 +371,12 @@ class ParticleFilter:
         self.loglik = torch.empty(K, dtype=torch.float64, device=dev)
         nb = C.c_size_t()
         _check(lib().lx_pf_workspace_size(P, net.N, net.M, C.byref(nb)), "lx_pf_workspace_size")
-        self.work = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
-        base = self.work.data_ptr()
-        aligned = (base + 255) // 256 * 256
+        if workspace:
+            self.work = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
+            base = self.work.data_ptr()
+            aligned = (base + 255) // 256 * 256
+        else:
+            self.work, aligned, nb = None, None, C.c_size_t(0)
         pb = PfProblem()
         pb.net = net.handle.value
         pb.P, pb.K, pb.obs_species = P, K, obs_species
@@ -374,6 +399,10 @@ class ParticleFilter:
     def run(self, stream=None):
         _check(lib().lx_pf_run(C.byref(self.pb), self.eps, self.mode, C.byref(self.opts),
                                _stream_ptr(stream)), "lx_pf_run")
+
+    def run_static(self, stream=None):
+        _check(lib().lx_pf_run_static(C.byref(self.pb), self.eps, self.mode, C.byref(self.opts),
+                                      _stream_ptr(stream)), "lx_pf_run_static")
 
     def capture(self, stream):
         self.release()

@@ -217,6 +217,41 @@ def critical_decay(n_fast=1, n_slow=2) -> Network:
     return _net(f"critical_decay{n_fast}_{n_slow}", m, p, theta, x0)
 
 
+def mass_action_jacobian_terms(net: Network):
+    """The derivatives d g_j / d y_k of a mass-action network as polynomial
+    terms -- what a caller supplies as a symbolic Jacobian: for every
+    reaction j and reactant species k of it, the expansion of
+    C'(y_k, m_kj) prod_{i != k} C(y_i, m_ij), with C(y, 1) = y,
+    C(y, 2) = y^2/2 - y/2, C(y, 3) = y^3/6 - y^2/2 + y/3 and their derivatives.
+    Returns (rxn [T], wrt [T], coef [T], powers [T][N]) in the order
+    (j ascending, k ascending, terms by descending power of y_k, then of the
+    other species in ascending order)."""
+    poly = {1: {1: 1.0}, 2: {2: 0.5, 1: -0.5}, 3: {3: 1.0 / 6.0, 2: -0.5, 1: 1.0 / 3.0}}
+    dpoly = {1: {0: 1.0}, 2: {1: 1.0, 0: -0.5}, 3: {2: 0.5, 1: -1.0, 0: 1.0 / 3.0}}
+    rxn, wrt, coef, pows = [], [], [], []
+    N = net.N
+    for j in range(net.M):
+        species = [i for i in range(N) if net.m[j, i] > 0]
+        for k in species:
+            terms = [(1.0, np.zeros(N, np.int32))]
+            for i in species:
+                factor = dpoly[int(net.m[j, i])] if i == k else poly[int(net.m[j, i])]
+                out = []
+                for c, pw in terms:
+                    for e in sorted(factor, reverse=True):
+                        q = pw.copy()
+                        q[i] += e
+                        out.append((c * factor[e], q))
+                terms = out
+            for c, pw in terms:
+                rxn.append(j)
+                wrt.append(k)
+                coef.append(c)
+                pows.append(pw)
+    return (np.array(rxn, np.int32), np.array(wrt, np.int32), np.array(coef, np.float64),
+            np.array(pows, np.int32).reshape(len(pows), N))
+
+
 # --------------------------------------------------------------------------
 # Ensembles: per-particle parameters and initial states.
 # --------------------------------------------------------------------------

@@ -158,10 +158,22 @@ def test_step_decision_bit_exact(lxm, orc, name, mode, precision):
     assert np.array_equal(got["action"], ref["action"])
 
 
-@pytest.mark.parametrize("jacobian", [0, 1])
+def _user_terms(net, scale):
+    rxn, wrt, coef, pw = W.mass_action_jacobian_terms(net)
+    return rxn, wrt, coef * scale, pw
+
+
+@pytest.mark.parametrize("jacobian", [0, 1, "user", "user_rough"])
 @pytest.mark.parametrize("name", ["dimer", "dimer_stiff", "isomerisation", "schlogl"])
 def test_implicit_solve_bit_exact(lxm, orc, name, jacobian):
+    # jacobian: analytic (0), forward differences (1), the caller's terms equal
+    # to the mass-action derivative ("user") or 0.7 times it ("user_rough",
+    # an approximate Jacobian: Newton still converges, to the same root)
     net = NETS[name]
+    terms = None
+    if isinstance(jacobian, str):
+        terms = _user_terms(net, 0.7 if jacobian == "user_rough" else 1.0)
+        jacobian = 2
     rng = np.random.default_rng(21)
     Q = 1000
     x, th = _random_states(net, Q, rng)
@@ -170,9 +182,10 @@ def test_implicit_solve_bit_exact(lxm, orc, name, jacobian):
     res = orc.tau_select(net.m, net.p, th, x)
     Pj = rng.poisson(np.minimum(res["a"] * tau[:, None], 1e6))
     jc = np.where(rng.uniform(size=Q) < 0.3, rng.integers(0, net.M, Q), -1).astype(np.int32)
-    h = lxm.Network(net.m, net.p)
+    h = lxm.Network(net.m, net.p, jacobian_terms=terms)
     got = lxm.test_implicit(h, th, x, tau, Pj, jc, jacobian=jacobian)
-    ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc, jacobian=jacobian)
+    kw = {"jacobian_terms": terms} if terms is not None else {}
+    ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc, jacobian=jacobian, **kw)
     assert np.array_equal(got["ok"], ref["ok"])
     assert np.array_equal(got["iters"], ref["iters"])
     assert np.array_equal(got["k"], ref["k"])

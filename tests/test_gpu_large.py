@@ -146,7 +146,7 @@ def test_step_decision_bit_exact(lxm, orc, name, precision):
         assert ref["eq"].any()
 
 
-@pytest.mark.parametrize("jacobian", [0, 1])
+@pytest.mark.parametrize("jacobian", [0, 1, 2])
 def test_implicit_solve_48_bit_exact(lxm, orc, jacobian):
     net = STIFF
     assert net.N == 48
@@ -158,8 +158,14 @@ def test_implicit_solve_48_bit_exact(lxm, orc, jacobian):
     res = orc.tau_select(net.m, net.p, th, x)
     Pj = rng.poisson(np.minimum(res["a"] * tau[:, None], 1e6))
     jc = np.where(rng.uniform(size=Q) < 0.3, rng.integers(0, net.M, Q), -1).astype(np.int32)
-    got = lxm.test_implicit(_handle(lxm, net), th, x, tau, Pj, jc, jacobian=jacobian)
-    ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc, jacobian=jacobian)
+    if jacobian == 2:   # the caller's terms (the mass-action derivative)
+        terms = W.mass_action_jacobian_terms(net)
+        h = lxm.Network(net.m, net.p, jacobian_terms=terms)
+        got = lxm.test_implicit(h, th, x, tau, Pj, jc, jacobian=2)
+        ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc, jacobian=2, jacobian_terms=terms)
+    else:
+        got = lxm.test_implicit(_handle(lxm, net), th, x, tau, Pj, jc, jacobian=jacobian)
+        ref = orc.implicit(net.m, net.p, th, x, tau, Pj, jc, jacobian=jacobian)
     assert np.array_equal(got["ok"], ref["ok"])
     assert np.array_equal(got["iters"], ref["iters"])
     assert np.array_equal(got["k"], ref["k"])

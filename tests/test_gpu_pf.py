@@ -57,7 +57,8 @@ def _same(got, ref, what):
 
 def test_gamma_hook_bit_exact(lxm, orc):
     rng = np.random.default_rng(1)
-    shape = np.concatenate([np.full(5000, 1.0), rng.uniform(1, 50, 20000), 10 ** rng.uniform(2, 6, 5000)])
+    shape = np.concatenate([np.full(5000, 1.0), rng.uniform(1, 50, 20000), 10 ** rng.uniform(2, 6, 5000),
+                            rng.uniform(0.01, 1.0, 5000), [np.nextafter(1.0, 0.0)]])
     n = shape.shape[0]
     pid = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
     e = rng.integers(0, 100, n).astype(np.uint32)

@@ -552,3 +552,34 @@ def test_rare_events_match_oracle_elementwise(lxm, orc, case, precision, schedul
     assert_same(got, ref, f"{name}/{precision}/{schedule}")
     assert np.all(got["stats"]["status"] == 0)
     assert int(got["stats"][counter].astype(np.int64).sum()) >= minimum, counter
+
+
+@pytest.mark.parametrize("schedule", ["plain", "batched", "group4"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,t_end,scale", [("dimer_stiff", 3.0, 1.0), ("dimer_rathinam", 2.0, 1.0),
+                                              ("dimer_stiff", 3.0, 0.7)])
+def test_user_jacobian_matches_oracle_elementwise(lxm, orc, name, t_end, scale, precision,
+                                                  schedule):
+    # implicit leaps with the caller's derivative terms (lx_network_create_jac)
+    net = getattr(W, name)()
+    rxn, wrt, coef, pw = W.mass_action_jacobian_terms(net)
+    terms = (rxn, wrt, coef * scale, pw)
+    P = 300
+    theta = W.gamma_prior_theta(net, P, seed=31)
+    _, x0 = W.tile(net, P)
+    import torch
+    h = lxm.Network(net.m, net.p, jacobian_terms=terms)
+    kw = {"group4": dict(schedule="batched", lanes_per_traj=4)}.get(schedule, dict(schedule=schedule))
+    res = lxm.simulate(h, torch.as_tensor(theta, device="cuda"), torch.as_tensor(x0, device="cuda"),
+                       t_end, 0.03, "adaptive", precision=precision, jacobian="user", **kw)
+    torch.cuda.synchronize()
+    got = {"x": res["x"].cpu().numpy(), "r": res["r"].cpu().numpy(), "G": res["G"].cpu().numpy(),
+           "stats": lxm.stats_numpy(res["stats"])}
+    ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode="adaptive", precision=precision,
+                       jacobian="user", jacobian_terms=terms)
+    assert_same(got, ref, f"{name}/{precision}/{schedule}/user x{scale}")
+    assert got["stats"]["steps_implicit"].sum() > 0
+    # a network without terms refuses the user Jacobian
+    with pytest.raises(lxm.LxError):
+        lxm.simulate(_handle(lxm, net), torch.as_tensor(theta, device="cuda"),
+                     torch.as_tensor(x0, device="cuda"), 0.1, jacobian="user")

@@ -13,12 +13,17 @@ from paper_1608_07058_amd import workloads as W
 SEED = 160807058
 
 
-@pytest.mark.parametrize("shape", [1.0, 1.5, 2.5, 20.0, 500.0, 1e5])
+@pytest.mark.parametrize("shape", [0.05, 0.3, 0.7, 0.999, 1.0, 1.5, 2.5, 20.0, 500.0, 1e5])
 def test_gamma_law(orc, shape):
     n = 100000
     g = orc.gamma(np.full(n, shape), np.arange(n), 3, 2)
     assert stats.kstest(g, stats.gamma(shape).cdf).pvalue > 1e-3
     assert abs(g.mean() - shape) < 5 * math.sqrt(shape / n)
+
+
+def test_gamma_invalid_shape_is_nan(orc):
+    g = orc.gamma(np.array([0.0, -1.0, np.inf, np.nan]), np.arange(4), 3, 2)
+    assert np.all(np.isnan(g))
 
 
 def test_gamma_sites_differ(orc):
