@@ -87,6 +87,10 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="trajectories the oracle baseline runs (default: 8192 per network for "
                          "the set, all for the dimer, 1024 otherwise)")
+    ap.add_argument("--cycles", action="store_true",
+                    help="after timing, run each form once more in the variant with cycle "
+                         "timers and report the shares of the implicit solve spent on the "
+                         "Jacobian and on the LU (single-network workloads)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes --steps times "
                          "(calibrates the FETCH_SIZE / WRITE_SIZE counters)")
@@ -207,6 +211,20 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
     ms = sum(per) / len(per)
     r_total = int(out["r"].sum(dtype=torch.int64).item())
     stats = lx.stats_numpy(out["stats"])
+    shares = None
+    if args.cycles and segs == 1 and grid_times is None:
+        # one more launch in the variant with cycle timers (not timed): clock
+        # cycles per trajectory in the Jacobian assembly, the LU solves, the
+        # implicit solves and the whole trajectory, summed over trajectories
+        cyc = torch.zeros((wl.P, 4), dtype=torch.int64, device="cuda")
+        lx.simulate(h, theta, x0, wl.t_end, wl.eps, wl.mode, out=out, stream=stream,
+                    cycles=cyc.data_ptr(), **opts)
+        torch.cuda.synchronize()
+        c = cyc.sum(dim=0).tolist()
+        shares = {"jacobian_of_implicit": c[0] / c[2] if c[2] else None,
+                  "lu_of_implicit": c[1] / c[2] if c[2] else None,
+                  "implicit_of_trajectory": c[2] / c[3] if c[3] else None,
+                  "cycles": {"jacobian": c[0], "lu": c[1], "implicit": c[2], "trajectory": c[3]}}
     if segs > 1:
         import numpy as np
         stats = {f: totals[f] for f in ("attempts", "steps_ssa", "steps_explicit",
@@ -226,6 +244,7 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
         "steps_per_s": {m: float(stats["steps_" + m].sum()) / (ms / 1e3)
                         for m in ("ssa", "explicit", "implicit")},
         "rejections_per_trajectory": float(stats["rejections"].mean()),
+        "cycle_shares": shares,
         "lane_status_ok": bool((stats["status"] == 0).all()),
         "precision": opts["precision"],
         "schedule": opts["schedule"],

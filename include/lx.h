@@ -132,7 +132,13 @@ typedef struct lx_options {
                            with the count and the first one in lx_last_error().
                            The call is then synchronous.  0 (default): return at
                            once; statuses are in `stats` when the stream is done */
-  int32_t reserved[2];
+  uint64_t cycles;      /* 0 (default), or the device address of a uint64 [P][4] buffer:
+                           the simulation then runs a variant that reads the GPU clock
+                           and writes, per trajectory, the cycles spent in (0) assembling
+                           the implicit solve's Jacobian, (1) its LU solves, (2) the whole
+                           implicit solves (Newton iterations and count rounding) and (3)
+                           the whole trajectory.  Measurement only; results unchanged.
+                           lx_simulate and lx_simulate_grid, regroup 0 */
 } lx_options;
 
 /* Per-trajectory statistics (80 bytes). */

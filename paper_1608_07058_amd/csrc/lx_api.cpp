@@ -335,7 +335,7 @@ std::string named_net(const lx_network_s& n, int k) {
 std::string const_source(const lx::SimParams& p) {
   char buf[1024];
   snprintf(buf, sizeof(buf),
-           "#define LX_CONST 1\n"
+           "%s#define LX_CONST 1\n"
            "struct LxConst {\n"
            "  static constexpr double eps = %a, delta = %a, n_stiff = %a, k_ssa = %a, k_crit = %a,\n"
            "      lam_thr = %a, newton_tol = %a;\n"
@@ -343,7 +343,8 @@ std::string const_source(const lx::SimParams& p) {
            "  static constexpr int n_c = %d, n_ssa_ex = %d, n_ssa_im = %d, newton_maxit = %d,\n"
            "      kcap = %d, mode = %d, accumulate = %d, ssa_k = %d, regroup = %d, jacobian = %d;\n"
            "};\n",
-           p.eps, p.delta, p.n_stiff, p.k_ssa, p.k_crit, p.lam_thr, p.newton_tol, p.max_steps,
+           p.cycles ? "#define LX_TIMERS 1\n" : "", p.eps, p.delta, p.n_stiff, p.k_ssa, p.k_crit,
+           p.lam_thr, p.newton_tol, p.max_steps,
            p.n_c, p.n_ssa_ex, p.n_ssa_im, p.newton_maxit, p.kcap, p.mode, p.accumulate, p.ssa_k,
            p.regroup, p.jacobian);
   return buf;
@@ -564,6 +565,9 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
   prm->mode = mode;
   prm->accumulate = o.accumulate ? 1 : 0;
   prm->jacobian = o.jacobian;
+  prm->cycles = (unsigned long long*)(uintptr_t)o.cycles;
+  if (o.cycles && o.regroup > 0)
+    return fail(LX_E_INVALID, "cycle timers need regroup 0");
   return LX_OK;
 }
 
@@ -920,6 +924,7 @@ lx_status lx_simulate_set(int32_t K, const lx_set_item* items, double t_end, dou
   if (opt) o = *opt;
   else lx_options_default(&o);
   o.schedule = LX_SCHED_BATCHED;
+  if (o.cycles) return fail(LX_E_INVALID, "cycle timers apply to lx_simulate and lx_simulate_grid");
   long long total = 0;
   for (int k = 0; k < K; ++k) {
     const lx_set_item& it = items[k];
@@ -1139,6 +1144,7 @@ lx_status pf_check(const lx_pf_problem* pb, double eps, int32_t mode, const lx_o
     return fail(LX_E_INVALID, "workspace too small or not 256-byte aligned");
   if (opt) *o = *opt;
   else lx_options_default(o);
+  if (o->cycles) return fail(LX_E_INVALID, "cycle timers apply to lx_simulate and lx_simulate_grid");
   o->accumulate = 1;
   o->pid_base = 0;
   o->pid_stride = 1;

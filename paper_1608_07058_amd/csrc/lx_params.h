@@ -34,7 +34,16 @@ struct SimParams {
   const double* times;
   int* x_grid;
   int n_times;
+  // clock cycles per trajectory [P][4] (kernels compiled with LX_TIMERS)
+  unsigned long long* cycles;
 };
+
+// Cycle timers of the LX_TIMERS variant: LX_CLOCK reads the GPU's clock.
+#ifdef LX_TIMERS
+#define LX_CLOCK() __builtin_amdgcn_s_memtime()
+#else
+#define LX_CLOCK() 0ull
+#endif
 
 // Per-trajectory statistics (layout of the public lx_stats).
 // Method constants of a launch (the fields of SimParams named below).  A

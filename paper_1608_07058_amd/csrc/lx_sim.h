@@ -192,6 +192,8 @@ struct Lane {
   // counters
   u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip, n_cf;  // < 2^32: attempts are bounded by max_steps
   long long n_nit;
+  // clock cycles (LX_TIMERS): Jacobian assembly, LU solves, implicit solves, start
+  unsigned long long cy_jac, cy_lu, cy_imp, cy_t0;
 
   // The time the trajectory runs to now: t_end, or the next observation time.
   __device__ __forceinline__ double t_end_(const SimParams& prm) const {
@@ -234,6 +236,19 @@ struct Lane {
     implicit = false;
     ssa_left = 0;
     n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = n_cf = 0;
+    cy_jac = cy_lu = cy_imp = 0;
+    cy_t0 = LX_CLOCK();
+  }
+
+  // Cycle timers of the trajectory (LX_TIMERS variant) as row p of prm.cycles.
+  __device__ __forceinline__ void store_cycles(long long p, const SimParams& prm) const {
+#ifdef LX_TIMERS
+    unsigned long long* c = prm.cycles + p * 4;
+    c[0] = cy_jac;
+    c[1] = cy_lu;
+    c[2] = cy_imp;
+    c[3] = LX_CLOCK() - cy_t0;
+#endif
   }
 
   __device__ __forceinline__ void store(long long p, int* x_out, int* r_out, double* G_out,
@@ -652,6 +667,7 @@ struct Lane {
   // holds the Poisson draws P_j, on success the rounded counts.
   __device__ __forceinline__ bool implicit_counts(double tau, long long (&k)[M], int jc,
                                                   const SimParams& prm) {
+    const unsigned long long ti0 = LX_CLOCK();
     double ax[M], c[N], y[N];
 #pragma unroll
     for (int j = 0; j < M; ++j) ax[j] = th[j] * g[j];
@@ -690,6 +706,7 @@ struct Lane {
       }
       // d a_j / d y_k: analytic, forward differences (a_j re-evaluated with
       // y_k moved by the representable step h_k), or the caller's terms
+      const unsigned long long tj0 = LX_CLOCK();
       double yh[N], h[N];
       if (LXP(prm, jacobian) == 1) {
 #pragma unroll
@@ -715,7 +732,11 @@ struct Lane {
           A[i][kk] = (i == kk ? 1.0 : 0.0) - tau * s;
         }
       }
-      if (!lu_solve(A, b)) break;
+      const unsigned long long tl0 = LX_CLOCK();
+      cy_jac += tl0 - tj0;
+      const bool lu_ok = lu_solve(A, b);
+      cy_lu += LX_CLOCK() - tl0;
+      if (!lu_ok) break;
       double dmax = 0.0, ymax = 0.0;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -733,6 +754,7 @@ struct Lane {
     }
     if (!converged) {
       n_nfail += 1;
+      cy_imp += LX_CLOCK() - ti0;
       return false;
     }
     double gy[M];
@@ -752,6 +774,7 @@ struct Lane {
       if (kr > 1073741824.0) kr = 1073741824.0;
       k[j] = (long long)kr;
     }
+    cy_imp += LX_CLOCK() - ti0;
     return true;
   }
 
@@ -1027,6 +1050,7 @@ extern "C" __global__ void __launch_bounds__(LX_BLOCK)
     break;
   }
   lane.store(p, x_out, r_out, G_out, stats);
+  lane.store_cycles(p, prm);
 }
 #endif
 
@@ -1072,7 +1096,10 @@ __device__ __forceinline__ void run_batched(long long blk, const double* __restr
       if constexpr (LX_GRID_ON) {
         if (lane.grid_next(p, prm, sub == 0)) continue;
       }
-      if (sub == 0) lane.store(p, x_out, r_out, G_out, stats);
+      if (sub == 0) {
+        lane.store(p, x_out, r_out, G_out, stats);
+        lane.store_cycles(p, prm);
+      }
       long long pn = 0;
       if (sub == 0) pn = (long long)atomicAdd(next, 1ull);
       p = group_read<TPL>(pn, 0);

@@ -101,6 +101,8 @@ struct LaneL {
   int ssa_left;
   u32 n_ssa, n_ex, n_im, n_rej, n_nfail, n_clip, n_cf;
   long long n_nit;
+  // clock cycles (LX_TIMERS): Jacobian assembly, LU solves, implicit solves, start
+  unsigned long long cy_jac, cy_lu, cy_imp, cy_t0;
 
   // The time the trajectory runs to now: t_end, or the next observation time.
   __device__ __forceinline__ double t_end_(const SimParams& prm) const {
@@ -149,6 +151,8 @@ struct LaneL {
     implicit = false;
     ssa_left = 0;
     n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = n_cf = 0;
+    cy_jac = cy_lu = cy_imp = 0;
+    cy_t0 = LX_CLOCK();
   }
 
   // Observation times, as Lane::grid_next: record the state as row kt of
@@ -174,6 +178,17 @@ struct LaneL {
       for (int i = 0; i < N; ++i) row[i] = -1;
     }
     return false;
+  }
+
+  // Cycle timers of the trajectory (LX_TIMERS variant) as row p of prm.cycles.
+  __device__ __forceinline__ void store_cycles(long long p, const SimParams& prm) const {
+#ifdef LX_TIMERS
+    unsigned long long* c = prm.cycles + p * 4;
+    c[0] = cy_jac;
+    c[1] = cy_lu;
+    c[2] = cy_imp;
+    c[3] = LX_CLOCK() - cy_t0;
+#endif
   }
 
   __device__ __forceinline__ void store(long long p, int* x_out, int* r_out, double* G_out,
@@ -386,6 +401,7 @@ struct LaneL {
   // ascending reaction order, so every entry receives its terms in the order
   // of the per-entry sums of lx::Lane.
   __device__ __noinline__ bool implicit_counts(double tau, int* k, int jc, const SimParams& prm) {
+    const unsigned long long ti0 = LX_CLOCK();
     double ax[M], c[N], y[N], s[N], A[N * N], gy[M];
     for (int j = 0; j < M; ++j) ax[j] = th[j] * g_large<NET>(j, x);
     for (int i = 0; i < N; ++i) c[i] = (double)x[i];
@@ -402,6 +418,7 @@ struct LaneL {
     bool converged = false;
     for (int it = 0; it < LXP(prm, newton_maxit); ++it) {
       n_nit += 1;
+      const unsigned long long tj0 = LX_CLOCK();
       for (int i = 0; i < N; ++i) s[i] = 0.0;
       for (int q = 0; q < N * N; ++q) A[q] = 0.0;
       for (int j = 0; j < M; ++j) {
@@ -436,7 +453,11 @@ struct LaneL {
       for (int i = 0; i < N; ++i)
         for (int kk = 0; kk < N; ++kk)
           A[i * N + kk] = (i == kk ? 1.0 : 0.0) - tau * A[i * N + kk];
-      if (!lu_solve(A, b)) break;
+      const unsigned long long tl0 = LX_CLOCK();
+      cy_jac += tl0 - tj0;
+      const bool lu_ok = lu_solve(A, b);
+      cy_lu += LX_CLOCK() - tl0;
+      if (!lu_ok) break;
       double dmax = 0.0, ymax = 0.0;
       for (int i = 0; i < N; ++i) {
         y[i] = y[i] + b[i];
@@ -453,6 +474,7 @@ struct LaneL {
     }
     if (!converged) {
       n_nfail += 1;
+      cy_imp += LX_CLOCK() - ti0;
       return false;
     }
     for (int j = 0; j < M; ++j) gy[j] = g_large_y<NET>(j, y);
@@ -470,6 +492,7 @@ struct LaneL {
       if (kr > 1073741824.0) kr = 1073741824.0;
       k[j] = (int)kr;
     }
+    cy_imp += LX_CLOCK() - ti0;
     return true;
   }
 
@@ -650,6 +673,7 @@ __device__ __forceinline__ void run_large(long long blk, const double* __restric
         if (lane.grid_next(p, prm)) continue;
       }
       lane.store(p, x_out, r_out, G_out, stats);
+      lane.store_cycles(p, prm);
       p = (long long)atomicAdd(next, 1ull);
       has = p < hi;
       if (has) lane.load(p, theta, x0, r_out, G_out, prm);

@@ -66,7 +66,7 @@ class Options(C.Structure):
         ("newton_tol", C.c_double), ("newton_maxit", C.c_int32), ("block_size", C.c_int32),
         ("max_steps", C.c_int64), ("lanes_per_wave", C.c_int32), ("ssa_k", C.c_int32),
         ("blocks_per_cu", C.c_int32), ("pid_stride", C.c_uint32), ("regroup", C.c_int32), ("lanes_per_traj", C.c_int32), ("jacobian", C.c_int32),
-        ("check_lanes", C.c_int32), ("reserved", C.c_int32 * 2),
+        ("check_lanes", C.c_int32), ("cycles", C.c_uint64),
     ]
 
 
