@@ -106,11 +106,14 @@ typedef struct lx_options {
   double lambda_thr;    /* Poisson inversion below, PTRS above, default 30, in [1,30] */
   double newton_tol;    /* Newton stop: |dy|inf <= tol*max(1,|y|inf), default 1e-10 */
   int32_t newton_maxit; /* default 20 */
-  int32_t block_size;   /* threads per block (64..256, multiple of 64); 0 = default 64 */
+  int32_t block_size;   /* threads per block (64..256, multiple of 64); 0 = default (64
+                           plain, 256 batched); networks beyond 16 species or 32
+                           reactions always run 64 */
   int64_t max_steps;    /* attempt budget per trajectory      default 10^7 (< 2^32) */
   int32_t lanes_per_wave; /* batched: active lanes per wave, 4/8/16/32/64; 0 = chosen from P */
   int32_t ssa_k;        /* batched: SSA steps per leap iteration, 1..64; 0 = default 4 */
-  int32_t blocks_per_cu;/* batched: resident blocks per CU, 1..8; 0 = default 2 */
+  int32_t blocks_per_cu;/* batched: resident blocks per CU, 1..8; 0 = default 2 (4 for
+                           networks beyond 16 species or 32 reactions) */
   uint32_t pid_stride;  /* row p uses RNG particle id pid_base + p * pid_stride;
                            0 means 1 (interleaved ids for sharding or mixed sets) */
   int32_t regroup;      /* batched: every `regroup` iterations the lanes of a block are
@@ -173,9 +176,11 @@ const char* lx_last_error(void);
  * g_j(X) = prod_i C(X_i, m_ij) (distinct-combination convention).
  * Sizes: N <= 64, M <= 256.  Networks with N <= 16 and M <= 32 run kernels
  * whose per-lane state lives in registers; larger ones run kernels that keep
- * per-lane arrays in the lane-interleaved private segment and read the
- * stoichiometry as compressed tables (one lane per trajectory; no network
- * sets, no particle filter, lanes_per_traj and regroup must be 0).
+ * per-lane arrays in the lane-interleaved private segment, read the
+ * stoichiometry as compressed tables and solve implicit leaps cooperatively,
+ * the whole wave on one Newton system in LDS at a time (one lane per
+ * trajectory; no network sets, no particle filter, lanes_per_traj and
+ * regroup must be 0).
  * Errors: LX_E_INVALID for a bad table or a network above those sizes.
  * *out receives a handle owned by the caller and released with
  * lx_network_destroy. */

@@ -304,6 +304,14 @@ std::string network_source(const lx_network_s& n) {
     s << "  static constexpr int N = " << n.N << ";\n  static constexpr int M = " << n.M << ";\n";
     s << "  static constexpr int NPAIRS = " << n.npairs << ";\n";
     csr_src(s, "RX_PTR", "RX_SP", "RX_RO", n.ro, n.M, n.N, false, true);
+    {  // reaction of every reactant slot (the RX_SP order)
+      std::vector<int> rj;
+      for (int j = 0; j < n.M; ++j)
+        for (int i = 0; i < n.N; ++i)
+          if (n.ro[(size_t)j * n.N + i] > 0) rj.push_back(j);
+      if (rj.empty()) rj.push_back(0);
+      s << "  static constexpr int NSLOT = " << (int)rj.size() << ";\n" << vec_src("RX_J", rj);
+    }
     csr_src(s, "NJ_PTR", "NJ_SP", "NJ_V", n.nu, n.M, n.N, false, false);
     csr_src(s, "NI_PTR", "NI_RX", "NI_V", n.nu, n.N, n.M, true, false);
     s << vec_src("PHI", n.phi);
@@ -625,7 +633,11 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
                   "without regrouping (lanes_per_traj and regroup must be 0)");
     const bool batched = o.schedule == LX_SCHED_BATCHED;
     L->batched = true;
-    L->block = o.block_size ? o.block_size : (batched ? 256 : 64);
+    // one wave per block: every wave owns an LDS area for its cooperative
+    // implicit solves (the 48 x 48 system of a 48-species network is 18 KB)
+    if (o.block_size != 0 && o.block_size != 64)
+      return fail(LX_E_INVALID, "networks beyond 16 species or 32 reactions run 64-thread blocks");
+    L->block = 64;
     finish_params(o, true, &L->prm);
     st = get_kernel(net, "large", o.precision, L->block, "lx_sim_large", &L->fn, 1,
                     const_source(L->prm), grid, may_load);
@@ -638,7 +650,7 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
       if (st != LX_OK) return st;
       lanes = traj_per_wave(o, P, cus);
       const long long round = (long long)(L->block / 64) * lanes;
-      const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 2);
+      const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 4);
       per_block = (P + max_grid - 1) / max_grid;
       if (per_block < round) per_block = round;
     }
@@ -829,7 +841,7 @@ lx_status lx_network_prepare(lx_network net, int32_t precision, int32_t schedule
     return fail(LX_E_INVALID, "schedule must be LX_SCHED_*");
   if (block_size != 0 && (block_size < 64 || block_size > MAX_BLOCK || block_size % 64 != 0))
     return fail(LX_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
-  const int block = block_size ? block_size : (schedule == LX_SCHED_BATCHED ? 256 : 64);
+  const int block = net->large ? 64 : (block_size ? block_size : (schedule == LX_SCHED_BATCHED ? 256 : 64));
   // the kernel lx_simulate uses with default options, eps 0.03, adaptive mode
   lx_options o;
   lx_options_default(&o);

@@ -103,6 +103,12 @@ struct LaneL {
   long long n_nit;
   // clock cycles (LX_TIMERS): Jacobian assembly, LU solves, implicit solves, start
   unsigned long long cy_jac, cy_lu, cy_imp, cy_t0;
+  // the current leap's counts (Poisson draws, then the accepted counts)
+  int kd[M];
+  // an implicit leap parked for the wave's cooperative solve (coop_newton)
+  bool pend, pend_ok, pend_last;
+  double pend_tau;
+  int pend_jc;
 
   // The time the trajectory runs to now: t_end, or the next observation time.
   __device__ __forceinline__ double t_end_(const SimParams& prm) const {
@@ -153,6 +159,7 @@ struct LaneL {
     n_ssa = n_ex = n_im = n_rej = n_nit = n_nfail = n_clip = n_cf = 0;
     cy_jac = cy_lu = cy_imp = 0;
     cy_t0 = LX_CLOCK();
+    pend = false;
   }
 
   // Observation times, as Lane::grid_next: record the state as row kt of
@@ -357,145 +364,9 @@ struct LaneL {
     t = t + tau_s;
   }
 
-  // Dense LU with partial pivoting (first maximal pivot); A row-major N x N.
-  __device__ static bool lu_solve(double* A, double* b) {
-    for (int c = 0; c < N; ++c) {
-      int piv = c;
-      double best = __builtin_fabs(A[c * N + c]);
-      for (int rr = c + 1; rr < N; ++rr) {
-        const double v = __builtin_fabs(A[rr * N + c]);
-        if (v > best) {
-          best = v;
-          piv = rr;
-        }
-      }
-      if (!(best > 0.0)) return false;
-      if (piv != c) {
-        for (int q = 0; q < N; ++q) {
-          const double tmp = A[c * N + q];
-          A[c * N + q] = A[piv * N + q];
-          A[piv * N + q] = tmp;
-        }
-        const double tb = b[c];
-        b[c] = b[piv];
-        b[piv] = tb;
-      }
-      for (int rr = c + 1; rr < N; ++rr) {
-        const double l = A[rr * N + c] / A[c * N + c];
-        for (int q = c; q < N; ++q) A[rr * N + q] = A[rr * N + q] - l * A[c * N + q];
-        b[rr] = b[rr] - l * b[c];
-      }
-    }
-    for (int rr = N - 1; rr >= 0; --rr) {
-      double s = b[rr];
-      for (int q = rr + 1; q < N; ++q) s = s - A[rr * N + q] * b[q];
-      b[rr] = s / A[rr * N + rr];
-    }
-    return true;
-  }
-
-  // Implicit leap (Rathinam et al. 2003): Newton on
-  //   F(y) = y - c - tau sum_{j noncritical} nu_j a_j(y),
-  //   c = x + sum_j nu_j (P_j - tau a_j(x)) + nu_jc [fired],
-  // with the analytic Jacobian.  Sums over reactions are scattered in
-  // ascending reaction order, so every entry receives its terms in the order
-  // of the per-entry sums of lx::Lane.
-  __device__ __noinline__ bool implicit_counts(double tau, int* k, int jc, const SimParams& prm) {
-    const unsigned long long ti0 = LX_CLOCK();
-    double ax[M], c[N], y[N], s[N], A[N * N], gy[M];
-    for (int j = 0; j < M; ++j) ax[j] = th[j] * g_large<NET>(j, x);
-    for (int i = 0; i < N; ++i) c[i] = (double)x[i];
-    for (int j = 0; j < M; ++j) {
-      if (!ncr_(j)) continue;
-      const double d = (double)k[j] - tau * ax[j];
-      for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q)
-        c[NET::NJ_SP[q]] = c[NET::NJ_SP[q]] + (double)NET::NJ_V[q] * d;
-    }
-    if (jc >= 0)
-      for (int q = NET::NJ_PTR[jc]; q < NET::NJ_PTR[jc + 1]; ++q)
-        c[NET::NJ_SP[q]] = c[NET::NJ_SP[q]] + (double)NET::NJ_V[q];
-    for (int i = 0; i < N; ++i) y[i] = (double)x[i];
-    bool converged = false;
-    for (int it = 0; it < LXP(prm, newton_maxit); ++it) {
-      n_nit += 1;
-      const unsigned long long tj0 = LX_CLOCK();
-      for (int i = 0; i < N; ++i) s[i] = 0.0;
-      for (int q = 0; q < N * N; ++q) A[q] = 0.0;
-      for (int j = 0; j < M; ++j) {
-        if (!ncr_(j)) continue;
-        const double ay = th[j] * g_large_y<NET>(j, y);
-        for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q)
-          s[NET::NJ_SP[q]] = s[NET::NJ_SP[q]] + (double)NET::NJ_V[q] * ay;
-        for (int qk = NET::RX_PTR[j]; qk < NET::RX_PTR[j + 1]; ++qk) {
-          const int kk = NET::RX_SP[qk];
-          double d;
-          if (LXP(prm, jacobian) == 2) {  // the caller's derivative terms
-            d = th[j] * dg_user_large<NET>(qk, y);
-          } else if (LXP(prm, jacobian) == 1) {  // forward difference, as Lane::implicit_counts
-            const double yk = y[kk];
-            double yh;
-            const double hk = fd_step(yk, &yh);
-            y[kk] = yh;
-            const double ayh = th[j] * g_large_y<NET>(j, y);
-            y[kk] = yk;
-            d = (ayh - ay) / hk;
-          } else {
-            d = th[j] * dg_large<NET>(j, kk, y);
-          }
-          for (int q = NET::NJ_PTR[j]; q < NET::NJ_PTR[j + 1]; ++q) {
-            const int i = NET::NJ_SP[q];
-            A[i * N + kk] = A[i * N + kk] + (double)NET::NJ_V[q] * d;
-          }
-        }
-      }
-      double b[N];
-      for (int i = 0; i < N; ++i) b[i] = -((y[i] - c[i]) - tau * s[i]);
-      for (int i = 0; i < N; ++i)
-        for (int kk = 0; kk < N; ++kk)
-          A[i * N + kk] = (i == kk ? 1.0 : 0.0) - tau * A[i * N + kk];
-      const unsigned long long tl0 = LX_CLOCK();
-      cy_jac += tl0 - tj0;
-      const bool lu_ok = lu_solve(A, b);
-      cy_lu += LX_CLOCK() - tl0;
-      if (!lu_ok) break;
-      double dmax = 0.0, ymax = 0.0;
-      for (int i = 0; i < N; ++i) {
-        y[i] = y[i] + b[i];
-        const double ad = __builtin_fabs(b[i]);
-        const double ay_ = __builtin_fabs(y[i]);
-        dmax = dmax < ad ? ad : dmax;
-        ymax = ymax < ay_ ? ay_ : ymax;
-      }
-      if (!(dmax == dmax)) break;
-      if (dmax <= LXP(prm, newton_tol) * (ymax < 1.0 ? 1.0 : ymax)) {
-        converged = true;
-        break;
-      }
-    }
-    if (!converged) {
-      n_nfail += 1;
-      cy_imp += LX_CLOCK() - ti0;
-      return false;
-    }
-    for (int j = 0; j < M; ++j) gy[j] = g_large_y<NET>(j, y);
-    for (int j = 0; j < M; ++j) {
-      if (!ncr_(j)) {
-        k[j] = 0;
-        continue;
-      }
-      const double v = (tau * (th[j] * gy[j]) - tau * ax[j]) + (double)k[j];
-      double kr = __builtin_round(v);
-      if (kr < 0.0) {
-        kr = 0.0;
-        n_clip += 1;
-      }
-      if (kr > 1073741824.0) kr = 1073741824.0;
-      k[j] = (int)kr;
-    }
-    cy_imp += LX_CLOCK() - ti0;
-    return true;
-  }
-
+  // One leap attempt with the current plan.  An implicit leap draws its
+  // Poisson counts and then waits (pend) for the wave's cooperative Newton
+  // solve (coop_newton); finish_pending completes it.
   __device__ __forceinline__ void leap_attempt(const SimParams& prm, const Key& key) {
     const u32 ea = e;
     e = e + 1;
@@ -539,31 +410,48 @@ struct LaneL {
     const R lam_thr = (R)LXP(prm, lam_thr);
     // Counts fit int32: the samplers' means are at most 2^30 and the
     // implicit counts are clamped there.
-    int k[M];
     bool overflow = false;
     for (int j = 0; j < M; ++j) {
-      k[j] = 0;
+      kd[j] = 0;
       if (ncr_(j)) {
         const long long kj =
             poisson_sample_call<P>(a[j] * tau_rr, lam_thr, LXP(prm, kcap), key, pid, ea, (u32)j);
         overflow = overflow || kj < 0;
-        k[j] = (int)kj;
+        kd[j] = (int)kj;
       }
     }
     if (overflow) {
       status = LANE_LAMBDA_OVERFLOW;
       return;
     }
-    bool ok = true;
-    if (implicit) ok = implicit_counts(tau, k, jc, prm);
+    if (implicit) {
+      pend = true;
+      pend_tau = tau;
+      pend_jc = jc;
+      pend_last = last;
+      return;
+    }
+    leap_accept(tau, jc, last, true, prm);
+  }
+
+  // The implicit leap after its solve: counts in kd if pend_ok.
+  __device__ __forceinline__ void finish_pending(const SimParams& prm) {
+    pend = false;
+    leap_accept(pend_tau, pend_jc, pend_last, pend_ok, prm);
+  }
+
+  // The rest of a leap attempt once its counts kd are known (`ok`: an
+  // implicit solve converged, or an explicit leap).
+  __device__ __forceinline__ void leap_accept(double tau, int jc, bool last, bool ok,
+                                              const SimParams& prm) {
     int xn[N];
     bool big = false;
     if (ok) {
-      if (jc >= 0) k[jc] = 1;
+      if (jc >= 0) kd[jc] = 1;
       for (int i = 0; i < N; ++i) {
         long long v = x[i];
         for (int q = NET::NI_PTR[i]; q < NET::NI_PTR[i + 1]; ++q)
-          v = v + (long long)NET::NI_V[q] * k[NET::NI_RX[q]];
+          v = v + (long long)NET::NI_V[q] * kd[NET::NI_RX[q]];
         ok = ok && v >= 0;
         big = big || v > 2147483647LL;
         xn[i] = (int)v;
@@ -574,7 +462,7 @@ struct LaneL {
       tau_p = tau_p / (R)2;
       return;
     }
-    for (int j = 0; j < M; ++j) big = big || (long long)r[j] + k[j] > 2147483647LL;
+    for (int j = 0; j < M; ++j) big = big || (long long)r[j] + kd[j] > 2147483647LL;
     if (big) {
       status = LANE_COUNT_OVERFLOW;
       return;
@@ -584,7 +472,7 @@ struct LaneL {
       const double go = g_large<NET>(j, x);
       const double gn = g_large<NET>(j, xn);
       G[j] = G[j] + (tau * (go + gn)) * 0.5;
-      r[j] = r[j] + k[j];
+      r[j] = r[j] + kd[j];
     }
     for (int i = 0; i < N; ++i) x[i] = xn[i];
     t = last ? t_end_(prm) : t + tau;
@@ -641,8 +529,270 @@ struct LaneL {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Wave-cooperative implicit solve.  A lane whose leap is implicit parks it
+// (LaneL::pend); the wave then solves the parked leaps one after another,
+// all 64 lanes on one Newton system held in LDS: reactions spread over lanes
+// for the propensities and derivatives, species (rows) over lanes for the
+// residual, the Jacobian rows, the LU elimination and the update.  Partial
+// pivoting relabels rows instead of moving them (a row swap only renames
+// which stored row is which), so every entry receives exactly the operations
+// of the dense row-swapping LU, in the same order.
+// ---------------------------------------------------------------------------
+template <class NET>
+struct SolveArea {
+  static constexpr int N = NET::N, M = NET::M, W = (NET::M + 31) / 32, LD = NET::N + 1;
+  double A[NET::N * LD];  // row-major, row stride N + 1 (bank spread)
+  double b[NET::N], y[NET::N], c[NET::N], sol[NET::N];
+  double ax[NET::M], ay[NET::M];
+  double d[NET::NSLOT];  // d a_j / d y_k of every reactant slot
+  int k[NET::M];         // Poisson draws in, rounded counts out
+  const double* th;
+  double tau;
+  int jc, clips;
+  u32 ncr[W];
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Wave maximum of values >= 0 (a NaN counts as 0, as the sequential
+// max(m, v) = (m < v ? v : m) from 0 skips it).
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  v = v == v ? v : 0.0;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double w = __shfl_xor(v, o, 64);
+    v = v < w ? w : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// g_j(y) with y_k replaced by yk (a forward-difference evaluation).
+template <class NET>
+__device__ __forceinline__ double g_large_moved(int j, int k, const double* y, double yk) {
+  double gj = 1.0;
+  for (int q = NET::RX_PTR[j]; q < NET::RX_PTR[j + 1]; ++q) {
+    const int i = NET::RX_SP[q];
+    gj = gj * binom_real(i == k ? yk : y[i], NET::RX_RO[q]);
+  }
+  return gj;
+}
+
+// Solve the implicit leap parked by lane s (Rathinam et al. 2003: Newton on
+//   F(y) = y - c - tau sum_{j noncritical} nu_j a_j(y),
+//   c = x + sum_j nu_j (P_j - tau a_j(x)) + nu_jc [fired],
+// from y = x, with the analytic, forward-difference or caller-supplied
+// Jacobian and an LU with partial pivoting per iteration), then round the
+// counts.  Called by every lane of the wave; lane s's parked data goes in
+// and its counts, statistics and timers come back.
+template <class P, class NET, bool GRID>
+__device__ void coop_newton(LaneL<P, NET, GRID>& me, int s, SolveArea<NET>& S, const int* xcol_s,
+                            const SimParams& prm) {
+  constexpr int N = NET::N, M = NET::M, LD = SolveArea<NET>::LD;
+  const int lid = threadIdx.x & 63;
+  const bool mine = lid == s;
+  const unsigned long long ti0 = LX_CLOCK();
+  if (mine) {
+    S.tau = me.pend_tau;
+    S.jc = me.pend_jc;
+    S.th = me.th;
+    for (int w = 0; w < SolveArea<NET>::W; ++w) S.ncr[w] = me.ncrw[w];
+    for (int j = 0; j < M; ++j) S.k[j] = me.kd[j];
+  }
+  wave_sync();
+  const double tau = S.tau;
+  const int jc = S.jc;
+  const double* th = S.th;
+  const XSlot xs{const_cast<int*>(xcol_s)};
+  auto ncr = [&](int j) { return ((S.ncr[j >> 5] >> (j & 31)) & 1u) != 0u; };
+  // tau a_j(x) and c, y = x
+  for (int j = lid; j < M; j += 64) S.ax[j] = th[j] * g_large<NET>(j, xs);
+  wave_sync();
+  if (lid < N) {
+    const int i = lid;
+    double ci = (double)xs[i];
+    for (int q = NET::NI_PTR[i]; q < NET::NI_PTR[i + 1]; ++q) {
+      const int j = NET::NI_RX[q];
+      if (!ncr(j)) continue;
+      const double dj = (double)S.k[j] - tau * S.ax[j];
+      ci = ci + (double)NET::NI_V[q] * dj;
+    }
+    if (jc >= 0)
+      for (int q = NET::NJ_PTR[jc]; q < NET::NJ_PTR[jc + 1]; ++q)
+        if (NET::NJ_SP[q] == i) ci = ci + (double)NET::NJ_V[q];
+    S.c[i] = ci;
+    S.y[i] = (double)xs[i];
+  }
+  wave_sync();
+  bool converged = false;
+  int iters = 0;
+  unsigned long long cj = 0, cl = 0;
+  for (int it = 0; it < LXP(prm, newton_maxit); ++it) {
+    iters += 1;
+    const unsigned long long tj0 = LX_CLOCK();
+    // a_j(y) of the non-critical reactions
+    for (int j = lid; j < M; j += 64) S.ay[j] = ncr(j) ? th[j] * g_large_y<NET>(j, S.y) : 0.0;
+    // d a_j / d y_k of every reactant slot
+    for (int sl = lid; sl < NET::NSLOT; sl += 64) {
+      const int j = NET::RX_J[sl];
+      const int kk = NET::RX_SP[sl];
+      double dd = 0.0;
+      if (ncr(j)) {
+        if (LXP(prm, jacobian) == 2) {
+          dd = th[j] * dg_user_large<NET>(sl, S.y);
+        } else if (LXP(prm, jacobian) == 1) {
+          double yh;
+          const double hk = fd_step(S.y[kk], &yh);
+          const double ayh = th[j] * g_large_moved<NET>(j, kk, S.y, yh);
+          dd = (ayh - th[j] * g_large_y<NET>(j, S.y)) / hk;
+        } else {
+          dd = th[j] * dg_large<NET>(j, kk, S.y);
+        }
+      }
+      S.d[sl] = dd;
+    }
+    wave_sync();
+    // residual and Jacobian row of species i (terms in ascending reaction order)
+    if (lid < N) {
+      const int i = lid;
+      double si = 0.0;
+      double* Ai = S.A + i * LD;
+      for (int kk = 0; kk < N; ++kk) Ai[kk] = 0.0;
+      for (int q = NET::NI_PTR[i]; q < NET::NI_PTR[i + 1]; ++q) {
+        const int j = NET::NI_RX[q];
+        if (!ncr(j)) continue;
+        const double v = (double)NET::NI_V[q];
+        si = si + v * S.ay[j];
+        for (int sl = NET::RX_PTR[j]; sl < NET::RX_PTR[j + 1]; ++sl) {
+          const int kk = NET::RX_SP[sl];
+          Ai[kk] = Ai[kk] + v * S.d[sl];
+        }
+      }
+      S.b[i] = -((S.y[i] - S.c[i]) - tau * si);
+      for (int kk = 0; kk < N; ++kk) Ai[kk] = (i == kk ? 1.0 : 0.0) - tau * Ai[kk];
+    }
+    wave_sync();
+    const unsigned long long tl0 = LX_CLOCK();
+    cj += tl0 - tj0;
+    // LU with partial pivoting: lane i holds stored row i, at logical position lp
+    int lp = lid;
+    bool lu_ok = true;
+    for (int cc = 0; cc < N; ++cc) {
+      const bool cand = lid < N && lp >= cc;
+      const double v = cand ? __builtin_fabs(S.A[lid * LD + cc]) : -1.0;
+      // the first maximal |pivot| in logical order from cc; a NaN is never
+      // chosen, and a NaN at position cc fails the step
+      const double vm = (cand && v == v) ? v : -1.0;
+      const double best = wave_max_nonneg(vm < 0.0 ? 0.0 : vm);
+      const unsigned long long at_cc = __ballot(cand && lp == cc);
+      const int lane_cc = __ffsll((long long)at_cc) - 1;
+      const double vcc = __shfl(v, lane_cc, 64);
+      const int piv = wave_min_int((cand && vm == best && vm >= 0.0) ? lp : 0x7fffffff);
+      if (!(vcc == vcc) || !(best > 0.0) || piv == 0x7fffffff) {
+        lu_ok = false;
+        break;
+      }
+      if (lid < N) lp = lp == cc ? piv : (lp == piv ? cc : lp);
+      const int pr = __ffsll((long long)__ballot(lid < N && lp == cc)) - 1;
+      const double* Ap = S.A + pr * LD;
+      if (lid < N && lp > cc) {
+        double* Ai = S.A + lid * LD;
+        const double l = Ai[cc] / Ap[cc];
+        for (int q = cc; q < N; ++q) Ai[q] = Ai[q] - l * Ap[q];
+        S.b[lid] = S.b[lid] - l * S.b[pr];
+      }
+      wave_sync();
+    }
+    if (lu_ok) {
+      // back substitution, logical rows from the last (sequential)
+      for (int rr = N - 1; rr >= 0; --rr) {
+        if (lid < N && lp == rr) {
+          const double* Ai = S.A + lid * LD;
+          double sum = S.b[lid];
+          for (int q = rr + 1; q < N; ++q) sum = sum - Ai[q] * S.sol[q];
+          S.sol[rr] = sum / Ai[rr];
+        }
+        wave_sync();
+      }
+    }
+    cl += LX_CLOCK() - tl0;
+    if (!lu_ok) break;
+    double ad = 0.0, ayv = 0.0;
+    if (lid < N) {
+      const double yi = S.y[lid] + S.sol[lid];
+      S.y[lid] = yi;
+      ad = __builtin_fabs(S.sol[lid]);
+      ayv = __builtin_fabs(yi);
+    }
+    const double dmax = wave_max_nonneg(ad);
+    const double ymax = wave_max_nonneg(ayv);
+    wave_sync();
+    if (!(dmax == dmax)) break;
+    if (dmax <= LXP(prm, newton_tol) * (ymax < 1.0 ? 1.0 : ymax)) {
+      converged = true;
+      break;
+    }
+  }
+  // rounded counts of the non-critical reactions
+  int clips = 0;
+  if (converged) {
+    for (int j = lid; j < M; j += 64) {
+      if (!ncr(j)) {
+        S.k[j] = 0;
+        continue;
+      }
+      const double gy = g_large_y<NET>(j, S.y);
+      const double v = (tau * (th[j] * gy) - tau * S.ax[j]) + (double)S.k[j];
+      double kr = __builtin_round(v);
+      if (kr < 0.0) {
+        kr = 0.0;
+        clips += 1;
+      }
+      if (kr > 1073741824.0) kr = 1073741824.0;
+      S.k[j] = (int)kr;
+    }
+  }
+  clips = wave_sum_int(clips);
+  wave_sync();
+  if (mine) {
+    me.n_nit += iters;
+    me.pend_ok = converged;
+    if (converged) {
+      me.n_clip += (u32)clips;
+      for (int j = 0; j < M; ++j) me.kd[j] = S.k[j];
+    } else {
+      me.n_nfail += 1;
+    }
+    me.cy_jac += cj;
+    me.cy_lu += cl;
+    me.cy_imp += LX_CLOCK() - ti0;
+  }
+  wave_sync();
+}
+
 // Batched schedule for large networks: block-owned particle ranges refilled
 // from an LDS cursor, SSA bursts of up to ssa_k steps per leap iteration.
+// The loop runs while any lane of the wave has a trajectory, so that every
+// lane takes part in the cooperative solves of the implicit leaps parked in
+// an iteration.
 template <class NET>
 __device__ __forceinline__ void run_large(long long blk, const double* __restrict__ theta,
                                           const int* __restrict__ x0, int* x_out, int* r_out,
@@ -660,23 +810,38 @@ __device__ __forceinline__ void run_large(long long blk, const double* __restric
   long long p = lo + (long long)wave * prm.lanes + lane_id;
   bool has = lane_id < prm.lanes && p < hi;
   __shared__ int xlds[NET::N * LX_BLOCK];
+  __shared__ SolveArea<NET> areas[LX_BLOCK / 64];
+  SolveArea<NET>& S = areas[wave];
+  const int* xwave = xlds + (threadIdx.x & ~63);
   LaneL<LX_POLICY, NET, LX_GRID_ON> lane;
   lane.x.p = xlds + threadIdx.x;
+  lane.pend = false;
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
-  while (has) {
-    if (lane.active(prm)) {
+  while (__ballot(has) != 0ull) {
+    if (has && lane.active(prm)) {
       lane.ssa_burst(prm, key, LXP(prm, ssa_k));
       if (lane.active(prm) && !lane.in_ssa(prm)) lane.step(prm, key);
     }
-    if (!lane.active(prm)) {
-      if constexpr (LX_GRID_ON) {
-        if (lane.grid_next(p, prm)) continue;
+    // the implicit leaps parked in this iteration, one after another
+    unsigned long long pend = __ballot(has && lane.pend);
+    while (pend) {
+      const int s = __ffsll((long long)pend) - 1;
+      coop_newton(lane, s, S, xwave + s, prm);
+      pend &= pend - 1ull;
+    }
+    if (has) {
+      if (lane.pend) lane.finish_pending(prm);
+      if (!lane.active(prm)) {
+        bool again = false;
+        if constexpr (LX_GRID_ON) again = lane.grid_next(p, prm);
+        if (!again) {
+          lane.store(p, x_out, r_out, G_out, stats);
+          lane.store_cycles(p, prm);
+          p = (long long)atomicAdd(next, 1ull);
+          has = p < hi;
+          if (has) lane.load(p, theta, x0, r_out, G_out, prm);
+        }
       }
-      lane.store(p, x_out, r_out, G_out, stats);
-      lane.store_cycles(p, prm);
-      p = (long long)atomicAdd(next, 1ull);
-      has = p < hi;
-      if (has) lane.load(p, theta, x0, r_out, G_out, prm);
     }
   }
 }
@@ -726,7 +891,8 @@ extern "C" __global__ void __launch_bounds__(64)
   action[q] = act;
 }
 
-// Implicit-leap solve on fixed states (test hook).
+// Implicit-leap solve on fixed states (test hook): the production
+// cooperative solve, the wave taking its cases one after another.
 extern "C" __global__ void __launch_bounds__(64)
     lx_hook_implicit(const double* __restrict__ theta, const int* __restrict__ xs,
                      const double* __restrict__ tau, const long long* __restrict__ Pj,
@@ -734,22 +900,34 @@ extern "C" __global__ void __launch_bounds__(64)
                      lx::SimParams prm) {
   constexpr int M = LxNet::M;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= prm.P) return;
-  __shared__ int xlds[LxNet::N * LX_BLOCK];
+  const bool valid = q < prm.P;
+  __shared__ int xlds[LxNet::N * 64];
+  __shared__ lx::SolveArea<LxNet> S;
   lx::LaneL<lx::F64, LxNet> lane;
   lane.x.p = xlds + threadIdx.x;
   lx::SimParams p2 = prm;
   p2.accumulate = 0;
   p2.pid_base = 0;
-  lane.load(q, theta, xs, nullptr, nullptr, p2);
-  lane.propensities();
-  for (int w = 0; w < lane.W; ++w) lane.ncrw[w] = 0u;
-  for (int j = 0; j < M; ++j)
-    if (lane.a[j] > 0.0 && j != jc[q]) lane.set_bit(lane.ncrw, j);
-  int k[M];
-  for (int j = 0; j < M; ++j) k[j] = (int)Pj[q * M + j];
-  const bool ok = lane.implicit_counts(tau[q], k, jc[q], prm);
-  for (int j = 0; j < M; ++j) k_out[q * M + j] = ok ? k[j] : 0;
+  lane.pend = false;
+  if (valid) {
+    lane.load(q, theta, xs, nullptr, nullptr, p2);
+    lane.propensities();
+    for (int w = 0; w < lane.W; ++w) lane.ncrw[w] = 0u;
+    for (int j = 0; j < M; ++j)
+      if (lane.a[j] > 0.0 && j != jc[q]) lane.set_bit(lane.ncrw, j);
+    for (int j = 0; j < M; ++j) lane.kd[j] = (int)Pj[q * M + j];
+    lane.pend_tau = tau[q];
+    lane.pend_jc = jc[q];
+  }
+  unsigned long long pend = __ballot(valid);
+  while (pend) {
+    const int s = __ffsll((long long)pend) - 1;
+    lx::coop_newton(lane, s, S, xlds + s, prm);
+    pend &= pend - 1ull;
+  }
+  if (!valid) return;
+  const bool ok = lane.pend_ok;
+  for (int j = 0; j < M; ++j) k_out[q * M + j] = ok ? lane.kd[j] : 0;
   ok_out[q] = ok ? 1 : 0;
   it_out[q] = (int)lane.n_nit;
 }
