@@ -412,9 +412,10 @@ __device__ __forceinline__ long long poisson_ptrs(typename P::R lam, const Key& 
   return (long long)__builtin_floor((double)lam);
 }
 
-// The binary64 PTRS draw of a binary32 mean at or beyond 2^22, out of line: a
-// rare path, kept out of the callers' code and registers.
-__device__ __noinline__ long long poisson_wide(double lam, Key key, u32 pid, u32 e, u32 site) {
+// The binary64 PTRS draw of a binary32 mean at or beyond 2^22 (inline: an
+// out-of-line call costs the simulation kernels more registers than the
+// inlined sampler does).
+__device__ __forceinline__ long long poisson_wide(double lam, Key key, u32 pid, u32 e, u32 site) {
   return poisson_ptrs<F64>(lam, key, pid, e, site);
 }
 

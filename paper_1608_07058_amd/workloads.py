@@ -77,10 +77,12 @@ def dimer_stiff(scale=1000.0, x0=(10000, 0, 0)) -> Network:
 
 
 def dimer_rathinam(x0=(400, 798, 0)) -> Network:
-    """The stiff decaying-dimerizing set as Rathinam et al. (2003) pose it,
-    the third model of the paper's accuracy comparison: the same reactions as
-    ``dimer()`` with c = (1, 10, 1000, 0.1) and X0 = (400, 798, 0), where the
-    dimerization pair is near partial equilibrium from the start."""
+    """A stand-in for the stiff decaying-dimerizing model of the paper's
+    accuracy comparison (whose SBML file is not available): the reactions of
+    ``dimer()`` with c = (1, 10, 1000, 0.1) and X0 = (400, 798, 0), the
+    constants as the Rathinam et al. (2003) example is commonly stated --
+    recalled, not read from that paper or from this one.  The dimerization
+    pair is near partial equilibrium from the start."""
     base = dimer(x0)
     return _net("dimer_rathinam", base.m, base.p, [1.0, 10.0, 1000.0, 0.1], x0, base.species,
                 base.reactions)
