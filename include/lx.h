@@ -142,6 +142,15 @@ typedef struct lx_options {
                            implicit solves (Newton iterations and count rounding) and (3)
                            the whole trajectory.  Measurement only; results unchanged.
                            lx_simulate and lx_simulate_grid, regroup 0 */
+  int32_t tail_lanes;   /* batched, one lane per trajectory: once a block has no particles
+                           left to hand out and at most 64 / tail_lanes trajectories are
+                           still running in a wave, the wave gives each of them a group
+                           of tail_lanes lanes (as lanes_per_traj) to finish it; 0 = off
+                           (default), 2, 4, 8 or 16.  Results unchanged */
+  int32_t waves_per_simd; /* register budget: 0 = the compiler's choice (default), else
+                           1..8 -- the kernel is compiled to keep at least this many
+                           waves resident per SIMD (fewer registers per lane, spills if
+                           needed).  Results unchanged */
 } lx_options;
 
 /* Per-trajectory statistics (80 bytes). */

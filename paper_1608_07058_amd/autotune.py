@@ -1,9 +1,11 @@
 """Autotuner for the batched schedule.
 
 Sweeps the launch knobs of ``lx_simulate`` (active lanes per wave, SSA steps
-per leap iteration, block size, resident blocks per CU) on a given ensemble,
-times each setting with HIP events on the launch stream, and keeps the
-fastest.  The knobs never change results (every trajectory's actions are
+per leap iteration, block size, resident blocks per CU, lanes per
+trajectory) on a given ensemble, times each setting with HIP events on the
+launch stream, and keeps the fastest; then refines it one knob at a time
+with the register budget (waves per SIMD the kernel is compiled for) and the
+lane groups that finish each block's last trajectories.  The knobs never change results (every trajectory's actions are
 fixed by its particle id), so tuning is pure scheduling.  Results persist in a
 JSON file keyed by network, ensemble size, precision, mode and architecture.
 
@@ -78,12 +80,8 @@ def tune(lx, h, theta, x0, t_end, eps, mode, precision, grid=None, reps=2, log=N
         "stats": torch.empty((P, lx.STATS_WORDS), dtype=torch.int64, device="cuda"),
     }
     stream = torch.cuda.current_stream()
-    names = list(grid)
-    table = []
-    for values in itertools.product(*(grid[n] for n in names)):
-        opts = dict(zip(names, values))
-        if not valid(opts, P):
-            continue
+
+    def timed(opts):
         kw = dict(schedule="batched", precision=precision, **opts)
         lx.simulate(h, theta, x0, t_end, eps, mode, out=out, stream=stream, **kw)  # warm-up
         times = []
@@ -94,16 +92,56 @@ def tune(lx, h, theta, x0, t_end, eps, mode, precision, grid=None, reps=2, log=N
             b.record(stream)
             b.synchronize()
             times.append(a.elapsed_time(b))
-        ms = min(times)
+        return min(times)
+
+    names = list(grid)
+    table = []
+    for values in itertools.product(*(grid[n] for n in names)):
+        opts = dict(zip(names, values))
+        if not valid(opts, P):
+            continue
+        ms = timed(opts)
         table.append((opts, ms))
         if log:
             log(f"[tune] {opts} {ms:.3f} ms")
-    best = min(table, key=lambda t: t[1])
-    return best[0], table
+    best = min(table, key=lambda t: t[1])[0]
+    best, rows = refine(best, timed, log)
+    table += rows
+    return best, table
 
 
 # Knobs swept for a network set (lx_simulate_set): one lane per trajectory,
 # the set's blocks sized by the scheduler.
+# second stage: each value on top of the best setting, one knob at a time
+REFINE = {
+    "waves_per_simd": (1, 2, 3, 4),
+    "tail_lanes": (4, 8, 16),
+}
+
+
+def refine(best, timed, log=None):
+    """Try every REFINE value on top of `best` (a dict of options), keeping a
+    value when it is faster; `timed(opts)` returns milliseconds.  Returns the
+    new best and the rows tried."""
+    rows = []
+    best_ms = timed(best)
+    rows.append((dict(best), best_ms))
+    for name, values in REFINE.items():
+        for v in values:
+            opts = dict(best, **{name: v})
+            if name == "tail_lanes" and opts.get("lanes_per_traj", 1) > 1:
+                continue
+            if name == "tail_lanes" and opts.get("regroup", 0):
+                continue
+            ms = timed(opts)
+            rows.append((opts, ms))
+            if log:
+                log(f"[refine] {opts} {ms:.3f} ms")
+            if ms < best_ms:
+                best, best_ms = opts, ms
+    return best, rows
+
+
 SET_GRID = {
     "lanes_per_wave": (64,),
     "ssa_k": (4, 8, 16),
@@ -142,8 +180,7 @@ def tune_set(lx, items, t_end, eps, mode, precision, grid=None, reps=1, log=None
         for k in range(len(items)):
             outs[k] = res[k]
 
-    for values in itertools.product(*(grid[n] for n in names)):
-        opts = dict(zip(names, values))
+    def timed(opts):
         kw = dict(precision=precision, **opts)
         run(kw)  # warm-up
         times = []
@@ -154,12 +191,18 @@ def tune_set(lx, items, t_end, eps, mode, precision, grid=None, reps=1, log=None
             b.record(stream)
             b.synchronize()
             times.append(a.elapsed_time(b))
-        ms = min(times)
+        return min(times)
+
+    for values in itertools.product(*(grid[n] for n in names)):
+        opts = dict(zip(names, values))
+        ms = timed(opts)
         table.append((opts, ms))
         if log:
             log(f"[tune] {opts} {ms:.3f} ms")
-    best = min(table, key=lambda t: t[1])
-    return best[0], table
+    best = min(table, key=lambda t: t[1])[0]
+    best, rows = refine(best, timed, log)
+    table += rows
+    return best, table
 
 
 def save(key, options, ms, table, path=DEFAULT_FILE):
@@ -192,7 +235,7 @@ def main():
     x0 = torch.as_tensor(wl.x0[0], device="cuda")
     best, table = tune(lx, h, theta, x0, wl.t_end, wl.eps, wl.mode, args.precision,
                        log=lambda s: print(s, flush=True))
-    ms = min(t for _, t in table)
+    ms = min(t for o, t in table if o == best)
     key = key_of(net.m, net.p, wl.P, args.precision, wl.mode, wl.theta[0], wl.x0[0])
     save(key, best, ms, table, args.out)
     print(json.dumps({"key": key, "best": best, "ms": ms}), flush=True)
@@ -208,7 +251,7 @@ def main_set(args, torch, lx, W):
              for k, (h, t, x) in enumerate(zip(hs, wl.theta, wl.x0))]
     best, table = tune_set(lx, items, wl.t_end, wl.eps, wl.mode, args.precision,
                            log=lambda s: print(s, flush=True))
-    ms = min(t for _, t in table)
+    ms = min(t for o, t in table if o == best)
     key = key_of_set([(n.m, n.p) for n in wl.nets], wl.P, args.precision, wl.mode)
     save(key, best, ms, table, args.out)
     print(json.dumps({"key": key, "best": best, "ms": ms}), flush=True)

@@ -33,7 +33,7 @@
 
 static_assert(sizeof(lx_stats) == sizeof(lx::Stats), "lx_stats layout");
 static_assert(sizeof(lx_stats) == 80, "lx_stats size");
-static_assert(sizeof(lx_options) == 152, "lx_options size");
+static_assert(sizeof(lx_options) == 160, "lx_options size");
 
 // Launchers of the static hook kernels (lx_hooks.hip).
 hipError_t lxh_launch_philox(long long, const unsigned*, const unsigned*, unsigned*, hipStream_t);
@@ -341,20 +341,23 @@ std::string named_net(const lx_network_s& n, int k) {
 // lx_params.h): one kernel per set of values; doubles in hexadecimal so the
 // constants are the exact binary64 values of the options.
 std::string const_source(const lx::SimParams& p) {
+  char waves[40] = "";
+  if (p.waves) snprintf(waves, sizeof(waves), "#define LX_WAVES %d\n", p.waves);
   char buf[1024];
   snprintf(buf, sizeof(buf),
-           "%s#define LX_CONST 1\n"
+           "%s%s#define LX_CONST 1\n"
            "struct LxConst {\n"
            "  static constexpr double eps = %a, delta = %a, n_stiff = %a, k_ssa = %a, k_crit = %a,\n"
            "      lam_thr = %a, newton_tol = %a;\n"
            "  static constexpr long long max_steps = %lldLL;\n"
            "  static constexpr int n_c = %d, n_ssa_ex = %d, n_ssa_im = %d, newton_maxit = %d,\n"
-           "      kcap = %d, mode = %d, accumulate = %d, ssa_k = %d, regroup = %d, jacobian = %d;\n"
+           "      kcap = %d, mode = %d, accumulate = %d, ssa_k = %d, regroup = %d, jacobian = %d,\n"
+           "      tail = %d;\n"
            "};\n",
-           p.cycles ? "#define LX_TIMERS 1\n" : "", p.eps, p.delta, p.n_stiff, p.k_ssa, p.k_crit,
+           p.cycles ? "#define LX_TIMERS 1\n" : "", waves, p.eps, p.delta, p.n_stiff, p.k_ssa, p.k_crit,
            p.lam_thr, p.newton_tol, p.max_steps,
            p.n_c, p.n_ssa_ex, p.n_ssa_im, p.newton_maxit, p.kcap, p.mode, p.accumulate, p.ssa_k,
-           p.regroup, p.jacobian);
+           p.regroup, p.jacobian, p.tail);
   return buf;
 }
 
@@ -392,7 +395,7 @@ std::string set_source(const std::vector<const lx_network_s*>& nets, int precisi
   src << lx_src_params << "\n" << lx_src_device << "\n";
   for (size_t k = 0; k < nets.size(); ++k) src << named_net(*nets[k], (int)k);
   src << "typedef LxNet0 LxNet;\n" << lx_src_sim << "\n";
-  src << "extern \"C\" __global__ void __launch_bounds__(LX_BLOCK)\n"
+  src << "extern \"C\" __global__ void __launch_bounds__(LX_BLOCK) LX_WAVES_ATTR\n"
          "    lx_sim_set(lx::SetArgs a, lx::SimParams prm) {\n"
          "  __shared__ unsigned long long next[" << nets.size() << "];\n"
          "  const long long blk = blockIdx.x;\n"
@@ -484,6 +487,8 @@ lx_status get_kernel(lx_network_s* net, const char* variant, int precision, int 
 void finish_params(const lx_options& o, bool batched, lx::SimParams* prm) {
   prm->ssa_k = batched ? (o.ssa_k ? o.ssa_k : 4) : 0;
   prm->regroup = batched ? o.regroup : 0;
+  prm->tail = (batched && o.lanes_per_traj <= 1 && o.regroup == 0 && !o.cycles) ? o.tail_lanes : 0;
+  prm->waves = o.waves_per_simd;
 }
 
 // Active lanes per wave of the batched schedule: full waves when the ensemble
@@ -540,6 +545,11 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
     return fail(LX_E_INVALID, "regroup needs one lane per trajectory");
   if (o.lanes_per_traj > 1 && o.lanes_per_wave != 0 && o.lanes_per_wave < o.lanes_per_traj)
     return fail(LX_E_INVALID, "lanes_per_wave must be at least lanes_per_traj");
+  if (o.tail_lanes != 0 && o.tail_lanes != 2 && o.tail_lanes != 4 && o.tail_lanes != 8 &&
+      o.tail_lanes != 16)
+    return fail(LX_E_INVALID, "tail_lanes must be 0, 2, 4, 8 or 16");
+  if (o.waves_per_simd < 0 || o.waves_per_simd > 8)
+    return fail(LX_E_INVALID, "waves_per_simd must be in [0, 8]");
   if (o.blocks_per_cu < 0 || o.blocks_per_cu > 8)
     return fail(LX_E_INVALID, "blocks_per_cu must be in [0, 8]");
   if (o.jacobian != LX_JAC_ANALYTIC && o.jacobian != LX_JAC_FD && o.jacobian != LX_JAC_USER)
@@ -627,10 +637,10 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
   if (net->large) {
     // One lane per trajectory; the plain schedule gives every lane one
     // trajectory, the batched one refills lanes from the block's range.
-    if (o.lanes_per_traj > 1 || o.regroup > 0)
+    if (o.lanes_per_traj > 1 || o.regroup > 0 || o.tail_lanes > 0)
       return fail(LX_E_UNSUPPORTED,
                   "networks beyond 16 species or 32 reactions run one lane per trajectory "
-                  "without regrouping (lanes_per_traj and regroup must be 0)");
+                  "without regrouping (lanes_per_traj, regroup and tail_lanes must be 0)");
     const bool batched = o.schedule == LX_SCHED_BATCHED;
     L->batched = true;
     // one wave per block: every wave owns an LDS area for its cooperative

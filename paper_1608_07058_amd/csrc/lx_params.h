@@ -29,6 +29,8 @@ struct SimParams {
   int lanes;              // active lanes per wave (4 to 64)
   int ssa_k;              // SSA steps a lane in an SSA burst takes per leap iteration
   int regroup;            // regroup lanes by next action every `regroup` iterations (0: never)
+  int tail;               // lanes per trajectory for the end of a block's range (0: off)
+  int waves;              // register budget: waves per SIMD the kernel is compiled for (0: default)
   // observation times (kernels compiled with LX_GRID): the state at
   // times[k], k < n_times, goes to x_grid [P][n_times][N]
   const double* times;
@@ -37,6 +39,13 @@ struct SimParams {
   // clock cycles per trajectory [P][4] (kernels compiled with LX_TIMERS)
   unsigned long long* cycles;
 };
+
+// Register budget of the simulation kernels (waves_per_simd option).
+#ifdef LX_WAVES
+#define LX_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(LX_WAVES)))
+#else
+#define LX_WAVES_ATTR
+#endif
 
 // Cycle timers of the LX_TIMERS variant: LX_CLOCK reads the GPU's clock.
 #ifdef LX_TIMERS

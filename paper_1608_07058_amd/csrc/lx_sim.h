@@ -1034,7 +1034,7 @@ struct Lane {
 
 #if !defined(LX_BATCHED) && !defined(LX_SET) && !defined(LX_LARGE)
 // Plain form: lane = particle for life, 64 lanes per wave.
-extern "C" __global__ void __launch_bounds__(LX_BLOCK)
+extern "C" __global__ void __launch_bounds__(LX_BLOCK) LX_WAVES_ATTR
     lx_sim_plain(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
                  int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1064,12 +1064,56 @@ namespace lx {
 // leap attempt, which balances the divergent paths (an SSA step costs a
 // fraction of a leap).  Per trajectory the sequence of actions, and hence
 // every result, is the one of the plain form.
+// The end of a block's range (tail_lanes): the n <= 64 / G trajectories still
+// running in the wave are saved to LDS and each is finished by a group of G
+// lanes (lane s of group g restores trajectory g), with the lane-group code
+// of lanes_per_traj; per trajectory the actions, and so the results, are
+// those of one lane.
+template <class NET, int G>
+__device__ __forceinline__ void finish_in_groups(Lane<LX_POLICY, NET, 1, LX_GRID_ON>& lane, bool has,
+                                                 long long p, const double* __restrict__ theta,
+                                                 int* x_out, int* r_out, double* G_out,
+                                                 Stats* stats, const SimParams& prm, u32* slots) {
+  typedef Lane<LX_POLICY, NET, 1, LX_GRID_ON> One;
+  constexpr int STRIDE = One::STATE_WORDS;
+  const int lane_id = threadIdx.x & 63;
+  const unsigned long long live = __ballot(has);
+  const int n = __popcll(live);
+  if (has) lane.save(p, slots + __popcll(live & ((1ull << lane_id) - 1ull)) * STRIDE);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int g = lane_id / G;
+  const int sub = lane_id & (G - 1);
+  if (g >= n) return;
+  const Key key{prm.k0, prm.k1};
+  Lane<LX_POLICY, NET, G, LX_GRID_ON> lg;
+  const long long pg = lg.restore(slots + g * STRIDE, theta, prm);
+  for (;;) {
+    if (lg.active(prm)) {
+      lg.ssa_burst(prm, key, LXP(prm, ssa_k));
+      if (lg.active(prm) && !lg.in_ssa(prm)) lg.step(prm, key);
+    }
+    if (!lg.active(prm)) {
+      if constexpr (LX_GRID_ON) {
+        if (lg.grid_next(pg, prm, sub == 0)) continue;
+      }
+      if (sub == 0) lg.store(pg, x_out, r_out, G_out, stats);
+      return;
+    }
+  }
+}
+
 template <class NET>
 __device__ __forceinline__ void run_batched(long long blk, const double* __restrict__ theta,
                                             const int* __restrict__ x0, int* x_out, int* r_out,
                                             double* G_out, Stats* stats, const SimParams& prm,
                                             unsigned long long* next, bool cursor_ready) {
   constexpr int TPL = LX_TPL;
+#ifdef LX_CONST
+  constexpr int TAIL = ::LxConst::tail;
+#else
+  constexpr int TAIL = 0;
+#endif
   const int lane_id = threadIdx.x & 63;
   const int slot = lane_id / TPL;  // trajectory slot of this lane in its wave
   const int sub = lane_id & (TPL - 1);
@@ -1087,6 +1131,38 @@ __device__ __forceinline__ void run_batched(long long blk, const double* __restr
   bool has = slot < prm.lanes && p < hi;
   Lane<LX_POLICY, NET, TPL, LX_GRID_ON> lane;
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
+  if constexpr (TPL == 1 && TAIL > 1) {
+    // wave-uniform loop: the wave switches to lane groups once the block's
+    // range is exhausted and few of its trajectories are left
+    __shared__ u32 tail_slots[(LX_BLOCK / 64) * (64 / (TAIL > 1 ? TAIL : 1)) *
+                              Lane<LX_POLICY, NET, 1, LX_GRID_ON>::STATE_WORDS];
+    u32* slots = tail_slots + wave * (64 / TAIL) * Lane<LX_POLICY, NET, 1, LX_GRID_ON>::STATE_WORDS;
+    for (;;) {
+      const unsigned long long live = __ballot(has);
+      if (!live) return;
+      if (__popcll(live) <= 64 / TAIL && *((volatile unsigned long long*)next) >= (unsigned long long)hi) {
+        finish_in_groups<NET, TAIL>(lane, has, p, theta, x_out, r_out, G_out, stats, prm, slots);
+        return;
+      }
+      if (has) {
+        if (lane.active(prm)) {
+          lane.ssa_burst(prm, key, LXP(prm, ssa_k));
+          if (lane.active(prm) && !lane.in_ssa(prm)) lane.step(prm, key);
+        }
+        if (!lane.active(prm)) {
+          bool again = false;
+          if constexpr (LX_GRID_ON) again = lane.grid_next(p, prm, true);
+          if (!again) {
+            lane.store(p, x_out, r_out, G_out, stats);
+            lane.store_cycles(p, prm);
+            p = (long long)atomicAdd(next, 1ull);
+            has = p < hi;
+            if (has) lane.load(p, theta, x0, r_out, G_out, prm);
+          }
+        }
+      }
+    }
+  }
   while (has) {
     if (lane.active(prm)) {
       lane.ssa_burst(prm, key, LXP(prm, ssa_k));
@@ -1211,7 +1287,7 @@ __device__ __forceinline__ void run_sched(long long blk, const double* __restric
 #endif
 
 #if defined(LX_BATCHED) && !defined(LX_LARGE)
-extern "C" __global__ void __launch_bounds__(LX_BLOCK)
+extern "C" __global__ void __launch_bounds__(LX_BLOCK) LX_WAVES_ATTR
     lx_sim_batched(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
                    int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
   __shared__ unsigned long long next;

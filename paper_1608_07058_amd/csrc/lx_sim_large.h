@@ -848,7 +848,7 @@ __device__ __forceinline__ void run_large(long long blk, const double* __restric
 }  // namespace lx
 
 #ifdef LX_LARGE
-extern "C" __global__ void __launch_bounds__(LX_BLOCK)
+extern "C" __global__ void __launch_bounds__(LX_BLOCK) LX_WAVES_ATTR
     lx_sim_large(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
                  int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {
   __shared__ unsigned long long next;

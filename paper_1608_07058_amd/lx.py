@@ -67,6 +67,7 @@ class Options(C.Structure):
         ("max_steps", C.c_int64), ("lanes_per_wave", C.c_int32), ("ssa_k", C.c_int32),
         ("blocks_per_cu", C.c_int32), ("pid_stride", C.c_uint32), ("regroup", C.c_int32), ("lanes_per_traj", C.c_int32), ("jacobian", C.c_int32),
         ("check_lanes", C.c_int32), ("cycles", C.c_uint64),
+        ("tail_lanes", C.c_int32), ("waves_per_simd", C.c_int32),
     ]
 
 
@@ -128,7 +129,7 @@ def lib():
             fn = getattr(L, name)
             if name not in ("lx_options_default", "lx_last_error"):
                 fn.restype = C.c_int32
-        if C.sizeof(Options) != 152:
+        if C.sizeof(Options) != 160:
             raise LxError("lx_options layout mismatch")
         _lib = L
     return _lib

@@ -40,7 +40,7 @@ def test_library_does_not_use_the_oracle():
 
 
 def test_struct_layouts_and_defaults():
-    assert C.sizeof(lx.Options) == 152
+    assert C.sizeof(lx.Options) == 160
     assert lx.STATS_DTYPE.itemsize == 80
     o = lx.options()
     assert (o.precision, o.schedule, o.n_c, o.n_ssa_ex, o.n_ssa_im, o.newton_maxit) == (0, 0, 10, 100, 10, 20)

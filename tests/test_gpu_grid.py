@@ -74,6 +74,7 @@ CASES = [
 
 SCHEDULES = {"plain": dict(schedule="plain"), "batched": dict(schedule="batched"),
              "regroup": dict(schedule="batched", regroup=1),
+             "tail8": dict(schedule="batched", tail_lanes=8, lanes_per_wave=64),
              "group4": dict(schedule="batched", lanes_per_traj=4)}
 
 

@@ -122,6 +122,30 @@ def test_random_network_full_ensemble_sampled(lxm, orc, precision):
         _same(sub, ref, f"random full/{precision}/p={p}")
 
 
+def test_random_network_full_horizon_sampled(lxm, orc):
+    # The whole random-network workload as bench.py times it: 65536
+    # trajectories to t_end 10 in one launch (batched mixed), implicit leaps
+    # with the cooperative 48 x 48 Newton solve included; 32 trajectories
+    # spread over the grid recomputed by the oracle must agree exactly, and
+    # every trajectory satisfies X = x0 + nu r.
+    wl = W.random_network_workload()
+    net = wl.nets[0]
+    theta, x0 = wl.theta[0], wl.x0[0]
+    got = _gpu(lxm, net, theta, x0, wl.t_end, "adaptive", precision="mixed", schedule="batched")
+    st = got["stats"]
+    assert np.all(st["status"] == 0)
+    assert st["steps_implicit"].sum() > 50 * wl.P
+    nu = (net.p - net.m).astype(np.int64)
+    assert np.array_equal(got["x"], x0 + got["r"].astype(np.int64) @ nu)
+    idx = np.unique(np.concatenate([np.arange(0, wl.P, wl.P // 30), [1, wl.P - 1]]))
+    for p in idx:
+        ref = orc.simulate(net.m, net.p, theta[p:p + 1], x0[p:p + 1], wl.t_end, mode="adaptive",
+                           precision="mixed", pid_base=int(p), nthreads=1)
+        sub = {"x": got["x"][p:p + 1], "r": got["r"][p:p + 1], "G": got["G"][p:p + 1],
+               "stats": got["stats"][p:p + 1]}
+        _same(sub, ref, f"random t_end 10/p={p}")
+
+
 def _states(net, Q, rng):
     scale = np.maximum(net.x0, 50)
     x = rng.integers(0, 3 * scale + 1, size=(Q, net.N))

@@ -110,9 +110,16 @@ def test_filter_graph_replays_match_direct_launches(lxm, orc):
     pf.release()
 
 
+def orc_pf_full(wl, net, K, y):
+    import oracle
+    return oracle.pf_run(net.m, net.p, wl.theta[0], wl.x0[0], K, 5.0, 3, 10.0, y,
+                         np.full(net.M, 2.0), 2.0 / net.theta, precision="mixed")
+
+
 def test_filter_full_size_runs(lxm):
-    # The particle-filter workload's shape: 2^18 particles; a few intervals here
-    # (the full 50 run in the benchmark-style check below).
+    # The particle-filter workload at its full size (2^18 particles, 50
+    # intervals of length 5) in one graph replay: invariants, then every
+    # output against the oracle's filter.
     import torch
     wl = W.telegraph_workload()
     net = wl.nets[0]
@@ -137,3 +144,8 @@ def test_filter_full_size_runs(lxm):
     assert np.array_equal(out["x"], wl.x0[0] + out["r"].astype(np.int64) @ nu)
     assert np.allclose(out["G"][:, 0] + out["G"][:, 1], 250.0, rtol=1e-12)
     pf.release()
+    # the whole filter, element by element, against the oracle's filter on the
+    # same inputs: every particle's theta, state, cumulative r and G after
+    # 50 resampling rounds, and the 50 log-likelihood increments
+    ref = orc_pf_full(wl, net, K, y)
+    _same(out, ref, "2^18 particles x 50 intervals")

@@ -86,15 +86,19 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("schedule", ["plain", "batched", "regroup", "group4"])
+@pytest.mark.parametrize("schedule", ["plain", "batched", "regroup", "group4", "tail4", "tail16"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision, schedule):
     name, net, mode, t_end, P = case
     theta = W.gamma_prior_theta(net, P, seed=7)
     _, x0 = W.tile(net, P)
+    # tail4/tail16: the last trajectories of each block finish in lane groups
     kw = {"regroup": dict(schedule="batched", regroup=1),
-          "group4": dict(schedule="batched", lanes_per_traj=4)}.get(schedule, dict(schedule=schedule))
+          "group4": dict(schedule="batched", lanes_per_traj=4),
+          "tail4": dict(schedule="batched", tail_lanes=4),
+          "tail16": dict(schedule="batched", tail_lanes=16, lanes_per_wave=64)}.get(
+              schedule, dict(schedule=schedule))
     got = gpu_run(lxm, net, theta, x0, t_end, mode, precision=precision, **kw)
     ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode=mode, precision=precision)
     assert_same(got, ref, f"{name}/{precision}/{schedule}")
@@ -407,9 +411,11 @@ def test_set_matches_oracle(lxm, orc, precision):
     got = _set_run(lxm, wl, precision)
     regrouped = _set_run(lxm, wl, precision, regroup=1, lanes_per_wave=16)
     grouped = _set_run(lxm, wl, precision, lanes_per_traj=2)
+    tailed = _set_run(lxm, wl, precision, tail_lanes=4, lanes_per_wave=64, block_size=128)
     for k, net in enumerate(wl.nets):
         assert_same(regrouped[k], got[k], f"{net.name} regrouped")
         assert_same(grouped[k], got[k], f"{net.name} lane groups")
+        assert_same(tailed[k], got[k], f"{net.name} tail lane groups")
         ref = orc.simulate(net.m, net.p, wl.theta[k], wl.x0[k], wl.t_end, mode=wl.mode,
                            precision=precision, pid_base=k, pid_stride=3)
         assert_same(got[k], ref, f"{net.name}/{precision}")
@@ -421,7 +427,8 @@ def test_set_matches_oracle(lxm, orc, precision):
 
 @pytest.mark.parametrize("knobs", [dict(), dict(blocks_per_cu=8, ssa_k=8),
                                    dict(regroup=2, lanes_per_wave=32, block_size=128),
-                                   dict(lanes_per_traj=4, blocks_per_cu=1)])
+                                   dict(lanes_per_traj=4, blocks_per_cu=1),
+                                   dict(tail_lanes=16, lanes_per_wave=64, blocks_per_cu=6)])
 def test_set_uneven_sizes(lxm, orc, knobs):
     # items of 0, 5 and 7001 trajectories: every block owns a slice of each
     # network, most blocks none of the small ones
@@ -534,6 +541,7 @@ EVENT_SCHEDULES = {
     "regroup": dict(schedule="batched", regroup=1),
     "group4": dict(schedule="batched", lanes_per_traj=4),
     "group16": dict(schedule="batched", lanes_per_traj=16),
+    "tail8": dict(schedule="batched", tail_lanes=8, lanes_per_wave=64),
 }
 
 
