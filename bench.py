@@ -36,6 +36,7 @@ METRIC = "trajectories/s and reaction-events/s on 1 GPU, batched-mixed vs plain 
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Device sources compiled into the simulation kernels at run time.
 KERNEL_SOURCES = ("lx_params.h", "lx_device.h", "lx_sim.h")
+LARGE_SOURCES = ("lx_sim_large.h", "lx_sim_wave.h")  # networks beyond 16 x 32
 PROFILES = os.path.join(ROOT, "profiles")
 # Workloads bench.py can time; the headline line is "mixed_set".
 WORKLOADS = {
@@ -109,13 +110,14 @@ def copy_calibration(args):
     print(json.dumps({"copy_bytes": n * 4, "copies": args.steps}), flush=True)
 
 
-def kernel_id(opts):
+def kernel_id(opts, large=False):
     """Hash of the kernel sources and the launch options of one form: HBM traffic
     measured with hardware counters is reported only for the kernel it was
-    measured on."""
+    measured on.  `large`: the network takes the large-network kernels, whose
+    sources are hashed too."""
     import hashlib
     h = hashlib.sha1()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES + (LARGE_SOURCES if large else ()):
         with open(os.path.join(ROOT, "paper_1608_07058_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     h.update(json.dumps(opts, sort_keys=True).encode())
@@ -231,8 +233,10 @@ def time_form(args, lx, h, theta, x0, wl, form, out):
                                         "steps_implicit", "rejections")}
         stats["status"] = np.full(1, 0 if totals["bad"] == 0 else 1)
     return {
-        "kernel_id": kernel_id(dict(opts, observation_times=args.times) if args.times else
-                               dict(opts, segments=segs) if segs > 1 else opts),
+        "kernel_id": kernel_id(dict(opts, workload=args.workload, observation_times=args.times)
+                               if args.times else
+                               dict(opts, workload=args.workload, segments=segs) if segs > 1 else
+                               dict(opts, workload=args.workload), large=h.large),
         "ms_per_step": ms,
         "wall_s": wall,
         "trajectories_per_s": wl.P / (ms / 1e3),

@@ -165,8 +165,10 @@ def lookup_set(nets, P, precision, mode, path=DEFAULT_FILE):
     return dict(load(path).get(key_of_set(nets, P, precision, mode), {}).get("options", {}))
 
 
-def tune_set(lx, items, t_end, eps, mode, precision, grid=None, reps=1, log=None):
-    """tune() for lx_simulate_set: ``items`` as for lx.simulate_set."""
+def tune_set(lx, items, t_end, eps, mode, precision, grid=None, reps=1, log=None, start=None):
+    """tune() for lx_simulate_set: ``items`` as for lx.simulate_set.  With
+    `start` (options), the grid is skipped and only the refine stage runs
+    from there."""
     import torch
     grid = grid or SET_GRID
     stream = torch.cuda.current_stream()
@@ -193,13 +195,16 @@ def tune_set(lx, items, t_end, eps, mode, precision, grid=None, reps=1, log=None
             times.append(a.elapsed_time(b))
         return min(times)
 
-    for values in itertools.product(*(grid[n] for n in names)):
-        opts = dict(zip(names, values))
-        ms = timed(opts)
-        table.append((opts, ms))
-        if log:
-            log(f"[tune] {opts} {ms:.3f} ms")
-    best = min(table, key=lambda t: t[1])[0]
+    if start is None:
+        for values in itertools.product(*(grid[n] for n in names)):
+            opts = dict(zip(names, values))
+            ms = timed(opts)
+            table.append((opts, ms))
+            if log:
+                log(f"[tune] {opts} {ms:.3f} ms")
+        best = min(table, key=lambda t: t[1])[0]
+    else:
+        best = {k: v for k, v in start.items() if k not in REFINE}
     best, rows = refine(best, timed, log)
     table += rows
     return best, table
@@ -220,6 +225,8 @@ def main():
                     choices=("dimer", "birth_death", "telegraph", "mixed_set", "dimer_rathinam"))
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--out", default=DEFAULT_FILE)
+    ap.add_argument("--refine-only", action="store_true",
+                    help="start from the stored knobs of the ensemble and run only the refine stage")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(HERE))
     import torch
@@ -249,10 +256,12 @@ def main_set(args, torch, lx, W):
     items = [{"net": h, "theta": torch.as_tensor(t, device="cuda"),
               "x0": torch.as_tensor(x, device="cuda"), "pid_base": k, "pid_stride": len(hs)}
              for k, (h, t, x) in enumerate(zip(hs, wl.theta, wl.x0))]
-    best, table = tune_set(lx, items, wl.t_end, wl.eps, wl.mode, args.precision,
-                           log=lambda s: print(s, flush=True))
-    ms = min(t for o, t in table if o == best)
     key = key_of_set([(n.m, n.p) for n in wl.nets], wl.P, args.precision, wl.mode)
+    start = load(args.out).get(key, {}).get("options") if args.refine_only else None
+    best, table = tune_set(lx, items, wl.t_end, wl.eps, wl.mode, args.precision,
+                           reps=2 if start else 1, log=lambda s: print(s, flush=True),
+                           start=start)
+    ms = min(t for o, t in table if o == best)
     save(key, best, ms, table, args.out)
     print(json.dumps({"key": key, "best": best, "ms": ms}), flush=True)
 

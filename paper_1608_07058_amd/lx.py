@@ -196,6 +196,11 @@ class Network:
         self._h = h
 
     @property
+    def large(self):
+        """Beyond 16 species or 32 reactions: the large-network kernels."""
+        return self.N > 16 or self.M > 32
+
+    @property
     def handle(self):
         return self._h
 

@@ -94,9 +94,10 @@ def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision, schedule
     theta = W.gamma_prior_theta(net, P, seed=7)
     _, x0 = W.tile(net, P)
     # tail4/tail16: the last trajectories of each block finish in lane groups
+    # (tail4 also compiled for at least two waves per SIMD)
     kw = {"regroup": dict(schedule="batched", regroup=1),
           "group4": dict(schedule="batched", lanes_per_traj=4),
-          "tail4": dict(schedule="batched", tail_lanes=4),
+          "tail4": dict(schedule="batched", tail_lanes=4, waves_per_simd=2),
           "tail16": dict(schedule="batched", tail_lanes=16, lanes_per_wave=64)}.get(
               schedule, dict(schedule=schedule))
     got = gpu_run(lxm, net, theta, x0, t_end, mode, precision=precision, **kw)
@@ -428,7 +429,8 @@ def test_set_matches_oracle(lxm, orc, precision):
 @pytest.mark.parametrize("knobs", [dict(), dict(blocks_per_cu=8, ssa_k=8),
                                    dict(regroup=2, lanes_per_wave=32, block_size=128),
                                    dict(lanes_per_traj=4, blocks_per_cu=1),
-                                   dict(tail_lanes=16, lanes_per_wave=64, blocks_per_cu=6)])
+                                   dict(tail_lanes=16, lanes_per_wave=64, blocks_per_cu=6,
+                                        waves_per_simd=3)])
 def test_set_uneven_sizes(lxm, orc, knobs):
     # items of 0, 5 and 7001 trajectories: every block owns a slice of each
     # network, most blocks none of the small ones
