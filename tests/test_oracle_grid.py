@@ -135,3 +135,24 @@ def test_structure_and_invalid_times(orc):
         assert np.all(g["x_grid"][ok, :first_bad] >= 0)
     with pytest.raises(ValueError):
         orc.simulate_grid(net.m, net.p, th, x0, [])
+
+
+def test_observation_times_keep_the_law_of_the_final_state(orc):
+    # Requesting observation times ends SSA bursts in progress there, so the
+    # step sequence (not the method's target law) depends on the times: the
+    # state at t_end with 20 observation times and without any must agree in
+    # distribution (independent streams).
+    net = W.dimer()
+    P = 12000
+    th, x0 = W.tile(net, P)
+    plain = orc.simulate(net.m, net.p, th, x0, 30.0, mode="adaptive", pid_base=0)
+    times = np.linspace(1.5, 30.0, 20)
+    g = orc.simulate_grid(net.m, net.p, th, x0, times, mode="adaptive", pid_base=1 << 20)
+    assert np.all(g["stats"]["status"] == 0) and np.all(plain["stats"]["status"] == 0)
+    assert g["stats"]["steps_ssa"].sum() > 0
+    for i in range(net.N):
+        a = plain["x"][:, i].astype(float)
+        b = g["x"][:, i].astype(float)
+        assert stats.ks_2samp(a, b).pvalue > 1e-3, i
+        se = np.sqrt(a.var() / P + b.var() / P)
+        assert abs(a.mean() - b.mean()) < 4.5 * se, (i, a.mean(), b.mean(), se)
