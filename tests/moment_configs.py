@@ -40,6 +40,8 @@ CONFIGS = {
     "C3 Schloegl, Gamma prior (t 50)": (
         W.schlogl, 50.0, "adaptive",
         lambda net, P, side: _prior(net, P, 321 if side == "gpu" else 322)),
+    "C4 random 48 x 128 network (t 1)": (
+        W.random_network, 1.0, "adaptive", lambda net, P, side: _tiled(net, P)),
     "C5 telegraph, Gamma prior, one interval (t 5)": (
         W.telegraph, 5.0, "adaptive",
         lambda net, P, side: _prior(net, P, 331 if side == "gpu" else 332)),
