@@ -124,6 +124,16 @@ def kernel_id(opts, large=False):
     return h.hexdigest()[:16]
 
 
+def kernel_name(net, form_result):
+    """The kernel a single-network form launches."""
+    large = net.N > 16 or net.M > 32
+    if large:
+        one_per_lane = (form_result["schedule"] == "plain"
+                        or form_result.get("options", {}).get("lanes_per_traj") == 1)
+        return "lx_sim_large" if one_per_lane else "lx_sim_wave"
+    return "lx_sim_" + form_result["schedule"]
+
+
 def recorded_traffic(kid):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) recorded
     in a profile summary for this kernel id, or None."""
@@ -607,7 +617,7 @@ def main():
                 "algorithmic_bytes": wl.P * (net.M * 8 + net.N * 4 + net.N * 4 + net.M * 4
                                              + net.M * 8 + lx.STATS_WORDS * 8),
                 "ops_per_trajectory": ops_per_traj,
-                "kernel": ("lx_sim_large" if net.N > 16 or net.M > 32 else "lx_sim_" + hr["schedule"]),
+                "kernel": kernel_name(net, hr),
                 "kernel_id": hr["kernel_id"]}
     dtype = "f32+f64" if hr["precision"] == "mixed" else "f64"
     line = {

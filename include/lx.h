@@ -108,7 +108,7 @@ typedef struct lx_options {
   int32_t newton_maxit; /* default 20 */
   int32_t block_size;   /* threads per block (64..256, multiple of 64); 0 = default (64
                            plain, 256 batched); networks beyond 16 species or 32
-                           reactions always run 64 */
+                           reactions run 64 with one trajectory per lane */
   int64_t max_steps;    /* attempt budget per trajectory      default 10^7 (< 2^32) */
   int32_t lanes_per_wave; /* batched: active lanes per wave, 4/8/16/32/64; 0 = chosen from P */
   int32_t ssa_k;        /* batched: SSA steps per leap iteration, 1..64; 0 = default 4 */
@@ -122,7 +122,9 @@ typedef struct lx_options {
   int32_t lanes_per_traj; /* batched: lanes per trajectory, 1, 2, 4, 8 or 16 (0 = 1); the lanes of a
                            trajectory split its Poisson draws and upcoming SSA draws;
                            lanes_per_wave counts lanes, so a wave holds
-                           lanes_per_wave / lanes_per_traj trajectories */
+                           lanes_per_wave / lanes_per_traj trajectories.  Networks
+                           beyond 16 species or 32 reactions: 0 = one trajectory per
+                           wave, 1 = one per lane */
   int32_t jacobian;     /* Jacobian of the implicit solve: LX_JAC_ANALYTIC (0, default,
                            the exact mass-action derivative, which is what a symbolic
                            Jacobian gives) or LX_JAC_FD (1, forward differences with the
@@ -147,7 +149,8 @@ typedef struct lx_options {
                            still running in a wave, the wave gives each of them a group
                            of tail_lanes lanes (as lanes_per_traj) to finish it; 0 = off
                            (default), 2, 4, 8 or 16.  Results unchanged */
-  int32_t waves_per_simd; /* register budget: 0 = the compiler's choice (default), else
+  int32_t waves_per_simd; /* register budget: 0 = the compiler's choice (default; 4 for
+                           the one-trajectory-per-wave kernel of large networks), else
                            1..8 -- the kernel is compiled to keep at least this many
                            waves resident per SIMD (fewer registers per lane, spills if
                            needed).  Results unchanged */
@@ -184,12 +187,14 @@ const char* lx_last_error(void);
  *   product_coeff     host int32 [M][N], p_ij >= 0 molecules produced.
  * g_j(X) = prod_i C(X_i, m_ij) (distinct-combination convention).
  * Sizes: N <= 64, M <= 256.  Networks with N <= 16 and M <= 32 run kernels
- * whose per-lane state lives in registers; larger ones run kernels that keep
- * per-lane arrays in the lane-interleaved private segment, read the
- * stoichiometry as compressed tables and solve implicit leaps cooperatively,
- * the whole wave on one Newton system in LDS at a time (one lane per
- * trajectory; no network sets, no particle filter, lanes_per_traj and
- * regroup must be 0).
+ * whose per-lane state lives in registers; larger ones run kernels that read
+ * the stoichiometry as compressed tables and solve implicit leaps with the
+ * whole wave on one Newton system in LDS: the batched schedule runs one
+ * trajectory per wave (reactions and species spread over the lanes, the
+ * waves of a block sharing the Newton area), the plain schedule, or the
+ * batched one with lanes_per_traj = 1, one trajectory per lane with its
+ * arrays in the lane-interleaved private segment (no network sets, no
+ * particle filter, lanes_per_traj at most 1, regroup and tail_lanes 0).
  * Errors: LX_E_INVALID for a bad table or a network above those sizes.
  * *out receives a handle owned by the caller and released with
  * lx_network_destroy. */

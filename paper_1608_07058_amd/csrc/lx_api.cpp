@@ -28,7 +28,7 @@
 #include <vector>
 
 #include "lx.h"
-#include "lx_embedded.inc"  // lx_src_params, lx_src_device, lx_src_sim, lx_src_sim_large (generated)
+#include "lx_embedded.inc"  // lx_src_params, lx_src_device, lx_src_sim, lx_src_sim_large, lx_src_sim_wave (generated)
 #include "lx_params.h"
 
 static_assert(sizeof(lx_stats) == sizeof(lx::Stats), "lx_stats layout");
@@ -72,6 +72,11 @@ lx_status hip_fail(hipError_t e, const char* what) {
 
 const int MAX_M = 256;  // networks up to 64 x 256 (large-network kernels beyond 16 x 32)
 const int MAX_N = 64;
+// Register budget of the one-trajectory-per-wave kernel when the caller
+// leaves waves_per_simd at 0: as many waves per SIMD as its LDS allows, at
+// most four (at most 128 registers); the compiler's own choice (about 200
+// registers, two waves) runs 1.5x slower on the random 48 x 128 ensemble.
+const int WAVE_KERNEL_WAVES = 4;
 const int REG_M = 32;  // register-resident kernels
 const int REG_N = 16;
 // The register-resident lane state needs well over 128 VGPRs; blocks of more
@@ -373,10 +378,13 @@ std::string kernel_source(const lx_network_s& net, const char* variant, int prec
   src << "#define LX_BLOCK " << block << "\n";
   if (strcmp(variant, "hooks") == 0) src << "#define LX_HOOKS 1\n";
   if (strcmp(variant, "batched") == 0) src << "#define LX_BATCHED 1\n";
+  const bool wave = strcmp(variant, "wave") == 0;
+  if (wave) src << "#define LX_WAVE 1\n";
   if (net.large) src << "#define LX_LARGE 1\n";
   src << consts << lx_src_params << "\n" << lx_src_device << "\n" << named_net(net, 0)
       << "typedef LxNet0 LxNet;\n" << lx_src_sim;
   if (net.large) src << "\n" << lx_src_sim_large;
+  if (net.large && wave) src << "\n" << lx_src_sim_wave;
   return src.str();
 }
 
@@ -626,6 +634,29 @@ struct SimLaunch {
   lx::SimParams prm;
 };
 
+// LDS bytes of a block of the one-trajectory-per-wave kernel (the layout of
+// WaveArea, SolveArea and the species' reaction lists in lx_sim_wave.h and
+// lx_sim_large.h), and from it the default register budget in waves per SIMD.
+int wave_default_waves(const lx_network_s& n, int precision, int block) {
+  const long long R = precision == LX_PREC_MIXED ? 4 : 8;
+  const long long MS = (n.M + 63) / 64, MP = 64 * MS, W = MP / 32;
+  long long nslot = 0, nni = 0;
+  for (int j = 0; j < n.M; ++j)
+    for (int i = 0; i < n.N; ++i) {
+      nslot += n.ro[(size_t)j * n.N + i] > 0;
+      nni += n.nu[(size_t)j * n.N + i] != 0;
+    }
+  auto up8 = [](long long b) { return (b + 7) / 8 * 8; };
+  const long long wave_area = up8(3 * MP * R + 4 * MP + 8LL * n.N + 4 * W + R);
+  const long long solve_area =
+      up8(8 * ((long long)n.N * (n.N + 1) + 4LL * n.N + 2LL * n.M + nslot) + 4LL * n.M + 24 +
+          4LL * ((n.M + 31) / 32));
+  const long long lds = (block / 64) * wave_area + solve_area + 2 * (nni + 1) + 16;
+  const long long blocks = 163840 / lds;
+  const long long reach = blocks * (block / 64) / 4;
+  return (int)(reach < 1 ? 1 : (reach > WAVE_KERNEL_WAVES ? WAVE_KERNEL_WAVES : reach));
+}
+
 lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end, double eps,
                    int32_t mode, SimLaunch* L, bool grid = false, bool may_load = true) {
   lx_status st = fill_params(o, P, t_end, eps, mode, &L->prm);
@@ -635,18 +666,43 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
                               "(lx_network_create_jac)");
   if (P == 0) return LX_OK;
   if (net->large) {
-    // One lane per trajectory; the plain schedule gives every lane one
-    // trajectory, the batched one refills lanes from the block's range.
+    // The batched schedule runs one trajectory per wave (lx_sim_wave), or with
+    // lanes_per_traj = 1 one per lane refilled from the block's range; the
+    // plain schedule gives every lane one trajectory.
     if (o.lanes_per_traj > 1 || o.regroup > 0 || o.tail_lanes > 0)
       return fail(LX_E_UNSUPPORTED,
-                  "networks beyond 16 species or 32 reactions run one lane per trajectory "
-                  "without regrouping (lanes_per_traj, regroup and tail_lanes must be 0)");
+                  "networks beyond 16 species or 32 reactions run one wave (batched) or one "
+                  "lane per trajectory without regrouping (lanes_per_traj 0 or 1, regroup and "
+                  "tail_lanes 0)");
     const bool batched = o.schedule == LX_SCHED_BATCHED;
     L->batched = true;
+    if (batched && o.lanes_per_traj == 0) {
+      // waves of a block share one LDS area for their implicit solves
+      L->block = o.block_size ? o.block_size : 256;
+      finish_params(o, true, &L->prm);
+      L->prm.ssa_k = 0;
+      if (L->prm.waves == 0) L->prm.waves = wave_default_waves(*net, o.precision, L->block);
+      st = get_kernel(net, "wave", o.precision, L->block, "lx_sim_wave", &L->fn, 1,
+                      const_source(L->prm), grid, may_load);
+      if (st != LX_OK) return st;
+      int cus = 0;
+      st = device_cus(&cus);
+      if (st != LX_OK) return st;
+      const long long round = L->block / 64;
+      const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 4);
+      long long per_block = (P + max_grid - 1) / max_grid;
+      if (per_block < round) per_block = round;
+      L->prm.per_block = per_block;
+      L->prm.lanes = 1;
+      L->grid = (P + per_block - 1) / per_block;
+      if (L->grid > 0x7fffffffLL) return fail(LX_E_INVALID, "P too large for one launch");
+      return LX_OK;
+    }
     // one wave per block: every wave owns an LDS area for its cooperative
     // implicit solves (the 48 x 48 system of a 48-species network is 18 KB)
     if (o.block_size != 0 && o.block_size != 64)
-      return fail(LX_E_INVALID, "networks beyond 16 species or 32 reactions run 64-thread blocks");
+      return fail(LX_E_INVALID, "networks beyond 16 species or 32 reactions run one lane per "
+                                "trajectory in 64-thread blocks");
     L->block = 64;
     finish_params(o, true, &L->prm);
     st = get_kernel(net, "large", o.precision, L->block, "lx_sim_large", &L->fn, 1,
@@ -851,7 +907,10 @@ lx_status lx_network_prepare(lx_network net, int32_t precision, int32_t schedule
     return fail(LX_E_INVALID, "schedule must be LX_SCHED_*");
   if (block_size != 0 && (block_size < 64 || block_size > MAX_BLOCK || block_size % 64 != 0))
     return fail(LX_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
-  const int block = net->large ? 64 : (block_size ? block_size : (schedule == LX_SCHED_BATCHED ? 256 : 64));
+  const bool wave = net->large && schedule == LX_SCHED_BATCHED;
+  const int block = wave ? (block_size ? block_size : 256)
+                         : net->large ? 64
+                                      : (block_size ? block_size : (schedule == LX_SCHED_BATCHED ? 256 : 64));
   // the kernel lx_simulate uses with default options, eps 0.03, adaptive mode
   lx_options o;
   lx_options_default(&o);
@@ -862,8 +921,12 @@ lx_status lx_network_prepare(lx_network net, int32_t precision, int32_t schedule
   if (st != LX_OK) return st;
   const bool batched = net->large || schedule == LX_SCHED_BATCHED;
   finish_params(o, batched, &prm);
+  if (wave) {
+    prm.ssa_k = 0;
+    if (prm.waves == 0) prm.waves = wave_default_waves(*net, precision, block);
+  }
   std::vector<char> code;
-  const char* variant = net->large ? "large" : (schedule == LX_SCHED_BATCHED ? "batched" : "plain");
+  const char* variant = wave ? "wave" : net->large ? "large" : (schedule == LX_SCHED_BATCHED ? "batched" : "plain");
   return compile_source(kernel_source(*net, variant, precision, block, 1, const_source(prm)), &code);
 }
 

@@ -596,32 +596,29 @@ __device__ __forceinline__ double g_large_moved(int j, int k, const double* y, d
   return gj;
 }
 
-// Solve the implicit leap parked by lane s (Rathinam et al. 2003: Newton on
+// The implicit leap of Rathinam et al. (2003), solved by the whole wave:
+// Newton on
 //   F(y) = y - c - tau sum_{j noncritical} nu_j a_j(y),
 //   c = x + sum_j nu_j (P_j - tau a_j(x)) + nu_jc [fired],
 // from y = x, with the analytic, forward-difference or caller-supplied
-// Jacobian and an LU with partial pivoting per iteration), then round the
-// counts.  Called by every lane of the wave; lane s's parked data goes in
-// and its counts, statistics and timers come back.
-template <class P, class NET, bool GRID>
-__device__ void coop_newton(LaneL<P, NET, GRID>& me, int s, SolveArea<NET>& S, const int* xcol_s,
-                            const SimParams& prm) {
+// Jacobian and an LU with partial pivoting per iteration, then the counts
+// rounded.  In: S.tau, S.jc, S.th, S.ncr and the Poisson draws S.k, species
+// counts xs; out: the rounded counts in S.k when the solve converged.
+// Called by every lane of the wave.
+struct NewtonOut {
+  int iters;
+  bool converged;
+  int clips;
+  unsigned long long cj, cl;  // cycles of Jacobian assembly and LU solves
+};
+
+template <class NET, class XV>
+__device__ __noinline__ NewtonOut newton_core(SolveArea<NET>& S, const XV& xs, const SimParams& prm) {
   constexpr int N = NET::N, M = NET::M, LD = SolveArea<NET>::LD;
   const int lid = threadIdx.x & 63;
-  const bool mine = lid == s;
-  const unsigned long long ti0 = LX_CLOCK();
-  if (mine) {
-    S.tau = me.pend_tau;
-    S.jc = me.pend_jc;
-    S.th = me.th;
-    for (int w = 0; w < SolveArea<NET>::W; ++w) S.ncr[w] = me.ncrw[w];
-    for (int j = 0; j < M; ++j) S.k[j] = me.kd[j];
-  }
-  wave_sync();
   const double tau = S.tau;
   const int jc = S.jc;
   const double* th = S.th;
-  const XSlot xs{const_cast<int*>(xcol_s)};
   auto ncr = [&](int j) { return ((S.ncr[j >> 5] >> (j & 31)) & 1u) != 0u; };
   // tau a_j(x) and c, y = x
   for (int j = lid; j < M; j += 64) S.ax[j] = th[j] * g_large<NET>(j, xs);
@@ -642,11 +639,9 @@ __device__ void coop_newton(LaneL<P, NET, GRID>& me, int s, SolveArea<NET>& S, c
     S.y[i] = (double)xs[i];
   }
   wave_sync();
-  bool converged = false;
-  int iters = 0;
-  unsigned long long cj = 0, cl = 0;
+  NewtonOut out{0, false, 0, 0ull, 0ull};
   for (int it = 0; it < LXP(prm, newton_maxit); ++it) {
-    iters += 1;
+    out.iters += 1;
     const unsigned long long tj0 = LX_CLOCK();
     // a_j(y) of the non-critical reactions
     for (int j = lid; j < M; j += 64) S.ay[j] = ncr(j) ? th[j] * g_large_y<NET>(j, S.y) : 0.0;
@@ -691,7 +686,7 @@ __device__ void coop_newton(LaneL<P, NET, GRID>& me, int s, SolveArea<NET>& S, c
     }
     wave_sync();
     const unsigned long long tl0 = LX_CLOCK();
-    cj += tl0 - tj0;
+    out.cj += tl0 - tj0;
     // LU with partial pivoting: lane i holds stored row i, at logical position lp
     int lp = lid;
     bool lu_ok = true;
@@ -733,7 +728,7 @@ __device__ void coop_newton(LaneL<P, NET, GRID>& me, int s, SolveArea<NET>& S, c
         wave_sync();
       }
     }
-    cl += LX_CLOCK() - tl0;
+    out.cl += LX_CLOCK() - tl0;
     if (!lu_ok) break;
     double ad = 0.0, ayv = 0.0;
     if (lid < N) {
@@ -747,13 +742,13 @@ __device__ void coop_newton(LaneL<P, NET, GRID>& me, int s, SolveArea<NET>& S, c
     wave_sync();
     if (!(dmax == dmax)) break;
     if (dmax <= LXP(prm, newton_tol) * (ymax < 1.0 ? 1.0 : ymax)) {
-      converged = true;
+      out.converged = true;
       break;
     }
   }
   // rounded counts of the non-critical reactions
   int clips = 0;
-  if (converged) {
+  if (out.converged) {
     for (int j = lid; j < M; j += 64) {
       if (!ncr(j)) {
         S.k[j] = 0;
@@ -770,19 +765,41 @@ __device__ void coop_newton(LaneL<P, NET, GRID>& me, int s, SolveArea<NET>& S, c
       S.k[j] = (int)kr;
     }
   }
-  clips = wave_sum_int(clips);
+  out.clips = wave_sum_int(clips);
   wave_sync();
+  return out;
+}
+
+// Solve the implicit leap parked by lane s (newton_core): lane s's parked
+// data goes in and its counts, statistics and timers come back.  Called by
+// every lane of the wave.
+template <class P, class NET, bool GRID>
+__device__ void coop_newton(LaneL<P, NET, GRID>& me, int s, SolveArea<NET>& S, const int* xcol_s,
+                            const SimParams& prm) {
+  constexpr int M = NET::M;
+  const int lid = threadIdx.x & 63;
+  const bool mine = lid == s;
+  const unsigned long long ti0 = LX_CLOCK();
   if (mine) {
-    me.n_nit += iters;
-    me.pend_ok = converged;
-    if (converged) {
-      me.n_clip += (u32)clips;
+    S.tau = me.pend_tau;
+    S.jc = me.pend_jc;
+    S.th = me.th;
+    for (int w = 0; w < SolveArea<NET>::W; ++w) S.ncr[w] = me.ncrw[w];
+    for (int j = 0; j < M; ++j) S.k[j] = me.kd[j];
+  }
+  wave_sync();
+  const NewtonOut o = newton_core<NET>(S, XSlot{const_cast<int*>(xcol_s)}, prm);
+  if (mine) {
+    me.n_nit += o.iters;
+    me.pend_ok = o.converged;
+    if (o.converged) {
+      me.n_clip += (u32)o.clips;
       for (int j = 0; j < M; ++j) me.kd[j] = S.k[j];
     } else {
       me.n_nfail += 1;
     }
-    me.cy_jac += cj;
-    me.cy_lu += cl;
+    me.cy_jac += o.cj;
+    me.cy_lu += o.cl;
     me.cy_imp += LX_CLOCK() - ti0;
   }
   wave_sync();
@@ -847,7 +864,7 @@ __device__ __forceinline__ void run_large(long long blk, const double* __restric
 }
 }  // namespace lx
 
-#ifdef LX_LARGE
+#if defined(LX_LARGE) && !defined(LX_WAVE)
 extern "C" __global__ void __launch_bounds__(LX_BLOCK) LX_WAVES_ATTR
     lx_sim_large(const double* __restrict__ theta, const int* __restrict__ x0, int* x_out,
                  int* r_out, double* G_out, lx::Stats* stats, lx::SimParams prm) {

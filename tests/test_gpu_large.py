@@ -1,6 +1,9 @@
-"""Networks beyond the register-resident kernels (lx_sim_large): the random
-48 x 128 mass-action network and a 48-species stiff network whose implicit
-leaps solve a 48 x 48 Newton system.
+"""Networks beyond the register-resident kernels: the random 48 x 128
+mass-action network and a 48-species stiff network whose implicit leaps solve
+a 48 x 48 Newton system.  Schedules: "plain" (lx_sim_large, one trajectory
+per lane), "batched" (lx_sim_wave, one trajectory per wave, 4-wave blocks
+sharing the Newton area), "wave64" (one wave per block) and "lane"
+(lx_sim_large refilling lanes from the block's range).
 
 The large-network kernels perform the operations of the oracle in the same
 order, so results are compared exactly, as for the small networks: whole
@@ -67,15 +70,19 @@ def _random_inputs(P):
 
 _REF = {}
 
+SCHED = {"plain": dict(schedule="plain"), "batched": dict(schedule="batched"),
+         "wave64": dict(schedule="batched", block_size=64),
+         "lane": dict(schedule="batched", lanes_per_traj=1)}
 
-@pytest.mark.parametrize("schedule", ["plain", "batched"])
+
+@pytest.mark.parametrize("schedule", ["plain", "batched", "wave64", "lane"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_random_network_elementwise(lxm, orc, precision, schedule):
     # 300 trajectories: several waves and a ragged tail; to t_end 0.2 a
     # trajectory takes ~4000 leaps, then SSA bursts (~20000 steps).
     net = RANDOM
     theta, x0 = _random_inputs(300)
-    got = _gpu(lxm, net, theta, x0, 0.2, "adaptive", precision=precision, schedule=schedule)
+    got = _gpu(lxm, net, theta, x0, 0.2, "adaptive", precision=precision, **SCHED[schedule])
     if precision not in _REF:
         _REF[precision] = orc.simulate(net.m, net.p, theta, x0, 0.2, mode="adaptive",
                                        precision=precision)
@@ -207,12 +214,13 @@ def test_large_network_limits(lxm):
     theta, x0 = _random_inputs(64)
     th = torch.as_tensor(theta, device="cuda")
     xi = torch.as_tensor(x0, device="cuda")
-    for bad in (dict(lanes_per_traj=4), dict(regroup=2)):
+    for bad in (dict(lanes_per_traj=4), dict(regroup=2), dict(tail_lanes=4),
+                dict(lanes_per_traj=1, block_size=128)):
         with pytest.raises(lxm.LxError):
             lxm.simulate(_handle(lxm, RANDOM), th, xi, 0.01, schedule="batched", **bad)
 
 
-@pytest.mark.parametrize("schedule", ["plain", "batched"])
+@pytest.mark.parametrize("schedule", ["plain", "batched", "lane"])
 def test_observation_times_elementwise(lxm, orc, schedule):
     # lx_simulate_grid on both large networks: states at every observation
     # time, X, r, G and statistics identical to the oracle's
@@ -224,7 +232,7 @@ def test_observation_times_elementwise(lxm, orc, schedule):
         res = lxm.simulate_grid(_handle(lxm, net), torch.as_tensor(theta, device="cuda"),
                                 torch.as_tensor(np.ascontiguousarray(x0, np.int32), device="cuda"),
                                 torch.as_tensor(times, device="cuda"), 0.03, mode,
-                                precision="mixed", schedule=schedule)
+                                precision="mixed", **SCHED[schedule])
         torch.cuda.synchronize()
         got = {"x_grid": res["x_grid"].cpu().numpy(), "x": res["x"].cpu().numpy(),
                "r": res["r"].cpu().numpy(), "G": res["G"].cpu().numpy(),
@@ -247,13 +255,13 @@ LARGE_EVENTS = [
 ]
 
 
-@pytest.mark.parametrize("schedule", ["plain", "batched"])
+@pytest.mark.parametrize("schedule", ["plain", "batched", "lane"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", LARGE_EVENTS, ids=[c[0] for c in LARGE_EVENTS])
 def test_large_rare_events_elementwise(lxm, orc, case, precision, schedule):
     name, net, mode, t_end, P, opts, counter, minimum = case
     theta, x0 = W.tile(net, P)
-    got = _gpu(lxm, net, theta, x0, t_end, mode, precision=precision, schedule=schedule, **opts)
+    got = _gpu(lxm, net, theta, x0, t_end, mode, precision=precision, **SCHED[schedule], **opts)
     ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode=mode, precision=precision, **opts)
     _same(got, ref, f"{name}/{precision}/{schedule}")
     assert np.all(got["stats"]["status"] == 0)
