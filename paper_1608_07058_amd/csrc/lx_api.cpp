@@ -637,7 +637,7 @@ struct SimLaunch {
 // LDS bytes of a block of the one-trajectory-per-wave kernel (the layout of
 // WaveArea, SolveArea and the species' reaction lists in lx_sim_wave.h and
 // lx_sim_large.h), and from it the default register budget in waves per SIMD.
-int wave_default_waves(const lx_network_s& n, int precision, int block) {
+long long wave_lds_bytes(const lx_network_s& n, int precision, int block) {
   const long long R = precision == LX_PREC_MIXED ? 4 : 8;
   const long long MS = (n.M + 63) / 64, MP = 64 * MS, W = MP / 32;
   long long nslot = 0, nni = 0;
@@ -651,8 +651,11 @@ int wave_default_waves(const lx_network_s& n, int precision, int block) {
   const long long solve_area =
       up8(8 * ((long long)n.N * (n.N + 1) + 4LL * n.N + 2LL * n.M + nslot) + 4LL * n.M + 24 +
           4LL * ((n.M + 31) / 32));
-  const long long lds = (block / 64) * wave_area + solve_area + 2 * (nni + 1) + 16;
-  const long long blocks = 163840 / lds;
+  return (block / 64) * wave_area + solve_area + 2 * (nni + 1) + 256;  // + cursor, lock, slack
+}
+
+int wave_default_waves(const lx_network_s& n, int precision, int block) {
+  const long long blocks = 163840 / wave_lds_bytes(n, precision, block);
   const long long reach = blocks * (block / 64) / 4;
   return (int)(reach < 1 ? 1 : (reach > WAVE_KERNEL_WAVES ? WAVE_KERNEL_WAVES : reach));
 }
@@ -677,8 +680,24 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
     const bool batched = o.schedule == LX_SCHED_BATCHED;
     L->batched = true;
     if (batched && o.lanes_per_traj == 0) {
-      // waves of a block share one LDS area for their implicit solves
-      L->block = o.block_size ? o.block_size : 256;
+      // waves of a block share one LDS area for their implicit solves; the
+      // block is the largest (up to 4 waves) whose LDS the device allows
+      int dev = 0, lds_max = 65536;
+      hipError_t e = hipGetDevice(&dev);
+      if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+      if (e != hipSuccess) return hip_fail(e, "device attributes");
+      if (o.block_size) {
+        L->block = o.block_size;
+      } else {
+        L->block = 256;
+        while (L->block > 64 && wave_lds_bytes(*net, o.precision, L->block) > lds_max)
+          L->block -= 64;
+      }
+      if (wave_lds_bytes(*net, o.precision, L->block) > lds_max)
+        return fail(LX_E_UNSUPPORTED, "the network's one-trajectory-per-wave kernel needs more LDS "
+                                      "per block than the device has (use a smaller block_size, "
+                                      "or lanes_per_traj = 1)");
       finish_params(o, true, &L->prm);
       L->prm.ssa_k = 0;
       if (L->prm.waves == 0) L->prm.waves = wave_default_waves(*net, o.precision, L->block);
@@ -908,7 +927,11 @@ lx_status lx_network_prepare(lx_network net, int32_t precision, int32_t schedule
   if (block_size != 0 && (block_size < 64 || block_size > MAX_BLOCK || block_size % 64 != 0))
     return fail(LX_E_INVALID, "block_size must be 0 or a multiple of 64 in [64, 256]");
   const bool wave = net->large && schedule == LX_SCHED_BATCHED;
-  const int block = wave ? (block_size ? block_size : 256)
+  int wave_block = block_size ? block_size : 256;
+  // without a device: the block a device with 64 KiB of LDS per block takes
+  while (wave && !block_size && wave_block > 64 && wave_lds_bytes(*net, precision, wave_block) > 65536)
+    wave_block -= 64;
+  const int block = wave ? wave_block
                          : net->large ? 64
                                       : (block_size ? block_size : (schedule == LX_SCHED_BATCHED ? 256 : 64));
   // the kernel lx_simulate uses with default options, eps 0.03, adaptive mode

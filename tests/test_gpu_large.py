@@ -63,6 +63,11 @@ RANDOM = W.random_network()
 STIFF = W.stiff_padded()
 
 
+# the largest size: 64 species, 256 reactions (four reaction slots per lane
+# in the one-trajectory-per-wave kernel)
+BIGGEST = W.random_network(seed=9, N=64, M=256, n_pairs=48, n_fast=6)
+
+
 def _random_inputs(P):
     wl = W.random_network_workload(P=P)
     return wl.theta[0], wl.x0[0]
@@ -88,6 +93,20 @@ def test_random_network_elementwise(lxm, orc, precision, schedule):
                                        precision=precision)
     _same(got, _REF[precision], f"random/{precision}/{schedule}")
     assert got["stats"]["steps_explicit"].sum() > 0 and got["stats"]["steps_ssa"].sum() > 0
+
+
+@pytest.mark.parametrize("schedule", ["plain", "batched", "lane"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_largest_network_elementwise(lxm, orc, precision, schedule):
+    # 64 x 256: the block of the one-trajectory-per-wave kernel is the largest
+    # whose LDS the device allows
+    net = BIGGEST
+    theta, x0 = W.tile(net, 96)
+    got = _gpu(lxm, net, theta, x0, 0.05, "adaptive", precision=precision, **SCHED[schedule])
+    ref = orc.simulate(net.m, net.p, theta, x0, 0.05, mode="adaptive", precision=precision)
+    _same(got, ref, f"64x256/{precision}/{schedule}")
+    assert np.all(got["stats"]["status"] == 0)
+    assert got["stats"]["steps_explicit"].sum() + got["stats"]["steps_ssa"].sum() > 0
 
 
 @pytest.mark.parametrize("mode", ["adaptive", "explicit", "ssa", "adaptive-fd"])
