@@ -104,6 +104,8 @@ def lib():
                                  C.c_int32, C.c_double, P, P, P, P, P, P, P, P,
                                  C.POINTER(Options)]
         L.orc_pf_run.restype = C.c_int
+        L.orc_pf_last_ops.argtypes = []
+        L.orc_pf_last_ops.restype = C.c_double
         assert L.orc_options_size() == C.sizeof(Options)
         assert L.orc_stats_size() == STATS_DTYPE.itemsize
         _lib = L
@@ -353,7 +355,9 @@ def resample(codes, k, *, seed=160807058, stream=0):
 
 
 def pf_run(m, p, theta, x0, K, dt, obs_species, obs_sd, y, alpha, beta, **kw):
-    """Particle filter (see orc_pf_run); returns theta, x, r, G, loglik."""
+    """Particle filter (see orc_pf_run); returns theta, x, r, G, loglik and ops,
+    the algorithmic operation count of its simulations (all particles and
+    intervals)."""
     m, p = _net_arrays(m, p)
     M, N = m.shape
     theta = np.array(theta, dtype=np.float64, copy=True)
@@ -372,4 +376,5 @@ def pf_run(m, p, theta, x0, K, dt, obs_species, obs_sd, y, alpha, beta, **kw):
                           _ptr(G), _ptr(ll), C.byref(o))
     if rc != 0:
         raise ValueError(f"oracle particle filter failed ({rc})")
-    return {"theta": theta, "x": x, "r": r, "G": G, "loglik": ll}
+    return {"theta": theta, "x": x, "r": r, "G": G, "loglik": ll,
+            "ops": float(lib().orc_pf_last_ops())}

@@ -1498,6 +1498,12 @@ void orc_resample(int64_t P, const uint64_t* codes, uint64_t seed, uint32_t stre
 // resampling; the new particles take their ancestors' state and cumulative
 // r, G, and draw theta_j ~ Gamma(alpha_j + r_j, rate beta_j + G_j).  loglik[k-1]
 // = max lw + log(sum of codes 2^-40 / P).  theta, x, r, G are in/out.
+// Algorithmic operations (count_ops) of the simulations of the last
+// orc_pf_run on this thread, summed over particles and intervals.
+static thread_local double g_pf_ops = 0.0;
+
+double orc_pf_last_ops() { return g_pf_ops; }
+
 int orc_pf_run(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab, int64_t P,
                int32_t K, double dt, int32_t obs_species, double obs_sd, const double* y,
                const double* alpha, const double* beta, double* theta, int32_t* x, int32_t* r,
@@ -1515,11 +1521,13 @@ int orc_pf_run(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab, i
   std::vector<int32_t> x2((size_t)P * N), r2((size_t)P * M);
   std::vector<double> G2((size_t)P * M);
   const double Lc = log_f64(obs_sd) + HALF_LOG_2PI_;
+  g_pf_ops = 0.0;
   for (int k = 1; k <= K; ++k) {
     o.t_start = (double)(k - 1) * dt;
     o.rng_stream = opt->rng_stream + (uint32_t)k;
     int rc = orc_simulate(N, M, mtab, ptab, P, theta, x, (double)k * dt, &o, x, r, G, st.data());
     if (rc != 0) return rc;
+    for (int64_t p = 0; p < P; ++p) g_pf_ops += (double)st[p].ops;
     double mx = -std::numeric_limits<double>::infinity();
     for (int64_t p = 0; p < P; ++p) {
       if (st[p].status != ST_OK) {
