@@ -462,7 +462,7 @@ def bench_pf(args, torch, lx, W):
     th0 = torch.as_tensor(wl.theta[0], device="cuda")
     x00 = torch.as_tensor(wl.x0[0], device="cuda")
     results = {}
-    for form in [f for f in args.forms.split(",") if f.startswith("batched")]:
+    for form in [f for f in args.forms.split(",") if f]:
         opts = dict(FORMS[form])
         if args.options:
             opts.update(json.loads(args.options))
@@ -498,7 +498,9 @@ def bench_pf(args, torch, lx, W):
         ll = pf.loglik.cpu().numpy()
         results[form] = {"ms_per_step": ms, "particle_intervals_per_s": wl.P * K / (ms / 1e3),
                          "loglik_finite": bool(np.isfinite(ll).all()),
-                         "precision": opts["precision"], "options": opts}
+                         "precision": opts["precision"], "schedule": opts["schedule"],
+                         "kernel_id": kernel_id(dict(opts, workload="telegraph_pf")),
+                         "options": opts}
         pf.release()
         log(args, f"[bench] {form}: {results[form]}")
     head = args.headline if args.headline in results else sorted(results)[0]
@@ -516,10 +518,27 @@ def bench_pf(args, torch, lx, W):
                "kind": "oracle", "sample": f"{n_cpu} particles x {K} intervals, fp64 oracle "
                                            f"filter, {nth} threads, {reps} x in {dtc:.1f} s",
                "per_core": reps * n_cpu * K / dtc / nth}
+        # the simulations' algorithmic operations, in the headline's precision,
+        # on the first particles, scaled to the filter (the weighting and
+        # resampling kernels stream a few bytes per particle)
+        n_ops = min(8192, wl.P)
+        ref = oracle.pf_run(net.m, net.p, wl.theta[0][:n_ops], wl.x0[0][:n_ops], K, dt, obs, sd,
+                            y, np.full(net.M, 2.0), 2.0 / net.theta, nthreads=nth,
+                            precision=hr["precision"])
+        ops_per_launch = ref["ops"] / n_ops * wl.P
+        roof = set_roofline(hr, ops_per_launch,
+                            f"oracle operation count ({hr['precision']}) of the simulations of "
+                            f"a {n_ops}-particle filter over the {K} intervals, scaled to "
+                            f"{wl.P} particles", wl.P, hr["kernel_id"])
+        roof["kernel"] = "lx_sim_" + hr["schedule"] + " (in the filter's graph)"
+    else:
+        roof = None
+    extra = {"forms": results, "roofline": roof, "cpu_baseline": cpu}
+    if "plain_fp64" in results and head != "plain_fp64":
+        extra["speedup_vs_plain_fp64"] = results["plain_fp64"]["ms_per_step"] / hr["ms_per_step"]
     line(args, "particle-intervals/s", hr["particle_intervals_per_s"], hr["ms_per_step"],
          "f32+f64" if hr["precision"] == "mixed" else "f64",
-         {"workload": wl.name, "particles": wl.P, "intervals": K, "dt": dt, "form": head},
-         {"forms": results, "roofline": None, "cpu_baseline": cpu})
+         {"workload": wl.name, "particles": wl.P, "intervals": K, "dt": dt, "form": head}, extra)
 
 
 def main():
@@ -541,7 +560,8 @@ def main():
     if args.times and args.segments > 1:
         raise SystemExit("--times and --segments are exclusive")
     if not args.forms:
-        args.forms = ("batched_mixed,plain_fp64,batched_fp64" if args.workload == "mixed_set"
+        args.forms = ("batched_mixed,plain_fp64,batched_fp64"
+                      if args.workload in ("mixed_set", "telegraph_pf")
                       else "batched_mixed,plain_fp64,plain_mixed,batched_fp64")
     if args.workload == "mixed_set":
         return bench_set(args, torch, lx, W)
