@@ -462,8 +462,13 @@ def bench_pf(args, torch, lx, W):
     th0 = torch.as_tensor(wl.theta[0], device="cuda")
     x00 = torch.as_tensor(wl.x0[0], device="cuda")
     results = {}
+    from paper_1608_07058_amd import autotune
     for form in [f for f in args.forms.split(",") if f]:
         opts = dict(FORMS[form])
+        if opts["schedule"] == "batched" and not args.untuned:
+            # knobs tuned on the first interval's ensemble, if any
+            opts.update(autotune.lookup(net.m, net.p, wl.P, opts["precision"], wl.mode,
+                                        wl.theta[0], wl.x0[0]))
         if args.options:
             opts.update(json.loads(args.options))
         th = th0.clone()

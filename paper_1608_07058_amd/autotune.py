@@ -34,6 +34,18 @@ GRID = {
 }
 
 
+# A smaller grid for ensembles too large to sweep the full one in minutes
+# (--grid small).
+SMALL_GRID = {
+    "lanes_per_traj": (1, 2, 4),
+    "lanes_per_wave": (64,),
+    "ssa_k": (4, 8, 16),
+    "block_size": (256,),
+    "blocks_per_cu": (2, 4),
+    "regroup": (0,),
+}
+
+
 def valid(opts, P):
     tpl = opts.get("lanes_per_traj", 1)
     if tpl > 1 and opts.get("regroup", 0):
@@ -225,6 +237,8 @@ def main():
                     choices=("dimer", "birth_death", "telegraph", "mixed_set", "dimer_rathinam"))
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--out", default=DEFAULT_FILE)
+    ap.add_argument("--grid", choices=("full", "small"), default="full",
+                    help="knob grid of single-network ensembles")
     ap.add_argument("--refine-only", action="store_true",
                     help="start from the stored knobs of the ensemble and run only the refine stage")
     args = ap.parse_args()
@@ -241,6 +255,7 @@ def main():
     theta = torch.as_tensor(wl.theta[0], device="cuda")
     x0 = torch.as_tensor(wl.x0[0], device="cuda")
     best, table = tune(lx, h, theta, x0, wl.t_end, wl.eps, wl.mode, args.precision,
+                       grid=SMALL_GRID if args.grid == "small" else None,
                        log=lambda s: print(s, flush=True))
     ms = min(t for o, t in table if o == best)
     key = key_of(net.m, net.p, wl.P, args.precision, wl.mode, wl.theta[0], wl.x0[0])

@@ -118,55 +118,75 @@ __global__ void __launch_bounds__(BLOCK)
   if (blockIdx.x == 0 && threadIdx.x == 0) *total_out = tot;
 }
 
+// Multinomial resampling: particle q draws its ancestor a(q), the smallest
+// a with scan[a] > U, U uniform on the integers below the total; then the
+// block's particles take their ancestors' state and cumulative r, G, and
+// draw theta_j ~ Gamma(alpha_j + r_j, rate beta_j + G_j).  The rows of the
+// block's particles are written together, consecutive threads writing
+// consecutive words.
 __global__ void __launch_bounds__(BLOCK)
     resample_kernel(long long P, int N, int M, const unsigned long long* __restrict__ scan,
                     const unsigned long long* __restrict__ total_in, lx::Key key, unsigned k,
                     const int* __restrict__ x, const int* __restrict__ r,
                     const double* __restrict__ G, int* x2, int* r2, double* G2, double* theta,
                     const double* __restrict__ alpha, const double* __restrict__ beta) {
-  const long long q = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (q >= P) return;
-  const unsigned long long S = *total_in;
-  const lx::Words4 w = lx::draw_block(key, (unsigned)q, k, lx::SITE_RESAMPLE, 0);
-  const unsigned long long r64 = ((unsigned long long)w.w0 << 32) | (unsigned long long)w.w1;
-  long long a;
-  if (S == 0) {  // every particle weighs zero: uniform resampling
-    a = (long long)__umul64hi(r64, (unsigned long long)P);
-  } else {
-    const unsigned long long U = __umul64hi(r64, S);
-    long long lo = 0, hi = P - 1;  // smallest a with scan[a] > U
-    while (lo < hi) {
-      const long long mid = (lo + hi) >> 1;
-      if (scan[mid] > U) hi = mid;
-      else lo = mid + 1;
+  __shared__ long long anc[BLOCK];
+  const long long q0 = (long long)blockIdx.x * BLOCK;
+  const long long q = q0 + threadIdx.x;
+  if (q < P) {
+    const unsigned long long S = *total_in;
+    const lx::Words4 w = lx::draw_block(key, (unsigned)q, k, lx::SITE_RESAMPLE, 0);
+    const unsigned long long r64 = ((unsigned long long)w.w0 << 32) | (unsigned long long)w.w1;
+    long long a;
+    if (S == 0) {  // every particle weighs zero: uniform resampling
+      a = (long long)__umul64hi(r64, (unsigned long long)P);
+    } else {
+      const unsigned long long U = __umul64hi(r64, S);
+      long long lo = 0, hi = P - 1;  // smallest a with scan[a] > U
+      while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (scan[mid] > U) hi = mid;
+        else lo = mid + 1;
+      }
+      a = lo;
     }
-    a = lo;
+    anc[threadIdx.x] = a;
   }
-  for (int i = 0; i < N; ++i) x2[q * N + i] = x[a * N + i];
-  for (int j = 0; j < M; ++j) {
+  __syncthreads();
+  const long long rest = P - q0;
+  const int nq = rest < BLOCK ? (int)rest : BLOCK;
+  for (int e = threadIdx.x; e < nq * N; e += BLOCK) {
+    const int qq = e / N, i = e - qq * N;
+    x2[(q0 + qq) * N + i] = x[anc[qq] * N + i];
+  }
+  for (int e = threadIdx.x; e < nq * M; e += BLOCK) {
+    const int qq = e / M, j = e - qq * M;
+    const long long a = anc[qq];
     const int rj = r[a * M + j];
     const double Gj = G[a * M + j];
-    r2[q * M + j] = rj;
-    G2[q * M + j] = Gj;
+    const long long o = (q0 + qq) * M + j;
+    r2[o] = rj;
+    G2[o] = Gj;
     const double shape = alpha[j] + (double)rj;
     const double rate = beta[j] + Gj;
-    theta[q * M + j] = lx::gamma_sample(shape, key, (unsigned)q, k, lx::SITE_GAMMA + (unsigned)j) / rate;
+    theta[o] = lx::gamma_sample(shape, key, (unsigned)(q0 + qq), k, lx::SITE_GAMMA + (unsigned)j) / rate;
   }
 }
 
+// The resampled state back into the caller's arrays (flat copies), and the
+// interval's log-likelihood.
 __global__ void __launch_bounds__(BLOCK)
     copyback_kernel(long long P, int N, int M, const int* __restrict__ x2,
                     const int* __restrict__ r2, const double* __restrict__ G2, int* x, int* r,
                     double* G, const double* mx, const unsigned long long* total, double* ll) {
-  const long long q = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (q < P) {
-    for (int i = 0; i < N; ++i) x[q * N + i] = x2[q * N + i];
-    for (int j = 0; j < M; ++j) {
-      r[q * M + j] = r2[q * M + j];
-      G[q * M + j] = G2[q * M + j];
-    }
+  const long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  const long long stride = (long long)gridDim.x * BLOCK;
+  for (long long e = t; e < P * N; e += stride) x[e] = x2[e];
+  for (long long e = t; e < P * M; e += stride) {
+    r[e] = r2[e];
+    G[e] = G2[e];
   }
-  if (q == 0) {
+  if (t == 0) {
     const unsigned long long S = *total;
     ll[0] = S == 0 ? -__builtin_inf()
                    : *mx + lx::log_f64(((double)S * 0x1p-40) / (double)P);
