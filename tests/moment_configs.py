@@ -27,22 +27,22 @@ def _prior(net, P, seed):
 
 # name -> (network factory, t_end, mode, inputs(P, side)); side is "gpu" or "oracle"
 CONFIGS = {
-    "C1 birth-death (t 100, explicit)": (
+    "birth-death (t 100, explicit)": (
         W.birth_death, 100.0, "explicit", lambda net, P, side: _tiled(net, P)),
-    "C2 decaying-dimerizing (t 30)": (
+    "decaying-dimerizing (t 30)": (
         W.dimer, 30.0, "adaptive", lambda net, P, side: _tiled(net, P)),
-    "C3 isomerisation, Gamma prior (t 50)": (
+    "isomerisation, Gamma prior (t 50)": (
         W.isomerisation, 50.0, "adaptive",
         lambda net, P, side: _prior(net, P, 301 if side == "gpu" else 302)),
-    "C3 birth-death, Gamma prior (t 50)": (
+    "birth-death, Gamma prior (t 50)": (
         W.birth_death, 50.0, "adaptive",
         lambda net, P, side: _prior(net, P, 311 if side == "gpu" else 312)),
-    "C3 Schloegl, Gamma prior (t 50)": (
+    "Schloegl, Gamma prior (t 50)": (
         W.schlogl, 50.0, "adaptive",
         lambda net, P, side: _prior(net, P, 321 if side == "gpu" else 322)),
-    "C4 random 48 x 128 network (t 1)": (
+    "random 48 x 128 network (t 1)": (
         W.random_network, 1.0, "adaptive", lambda net, P, side: _tiled(net, P)),
-    "C5 telegraph, Gamma prior, one interval (t 5)": (
+    "telegraph, Gamma prior, one interval (t 5)": (
         W.telegraph, 5.0, "adaptive",
         lambda net, P, side: _prior(net, P, 331 if side == "gpu" else 332)),
 }
