@@ -44,6 +44,7 @@ WORKLOADS = {
     "birth_death": "birth_death_workload",
     "dimer_rathinam": "rathinam_workload",    # implicit leaps (Jacobian variants via --options)
     "random48x128": "random_network_workload",
+    "stiff_padded45": "stiff_padded_workload",  # implicit leaps with 48 x 48 Newton systems
     "mixed_set": "mixed_set_workload",        # three networks in one launch (lx_simulate_set)
     "telegraph_pf": "telegraph_workload",     # the particle-filter interval loop (lx_pf_*)
 }

@@ -46,7 +46,17 @@ SMALL_GRID = {
 }
 
 
+# Networks beyond 16 species or 32 reactions (one trajectory per wave): the
+# block size sets how many waves share one Newton area in LDS.
+LARGE_GRID = {
+    "block_size": (64, 128, 192, 256),
+    "blocks_per_cu": (4,),
+}
+
+
 def valid(opts, P):
+    if "lanes_per_wave" not in opts:  # LARGE_GRID
+        return True
     tpl = opts.get("lanes_per_traj", 1)
     if tpl > 1 and opts.get("regroup", 0):
         return False
@@ -117,7 +127,7 @@ def tune(lx, h, theta, x0, t_end, eps, mode, precision, grid=None, reps=2, log=N
         if log:
             log(f"[tune] {opts} {ms:.3f} ms")
     best = min(table, key=lambda t: t[1])[0]
-    best, rows = refine(best, timed, log)
+    best, rows = refine(best, timed, log, large=getattr(h, "large", False))
     table += rows
     return best, table
 
@@ -131,14 +141,17 @@ REFINE = {
 }
 
 
-def refine(best, timed, log=None):
+def refine(best, timed, log=None, large=False):
     """Try every REFINE value on top of `best` (a dict of options), keeping a
     value when it is faster; `timed(opts)` returns milliseconds.  Returns the
-    new best and the rows tried."""
+    new best and the rows tried.  `large`: a network beyond 16 x 32, which
+    has no tail lane groups."""
     rows = []
     best_ms = timed(best)
     rows.append((dict(best), best_ms))
     for name, values in REFINE.items():
+        if large and name == "tail_lanes":
+            continue
         for v in values:
             opts = dict(best, **{name: v})
             if name == "tail_lanes" and opts.get("lanes_per_traj", 1) > 1:
@@ -234,7 +247,10 @@ def save(key, options, ms, table, path=DEFAULT_FILE):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--workload", default="dimer",
-                    choices=("dimer", "birth_death", "telegraph", "mixed_set", "dimer_rathinam"))
+                    choices=("dimer", "birth_death", "telegraph", "mixed_set", "dimer_rathinam",
+                             "random48x128", "stiff_padded45"))
+    ap.add_argument("--t-end", type=float, default=0.0,
+                    help="tune on a shorter horizon than the workload's (single networks)")
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--out", default=DEFAULT_FILE)
     ap.add_argument("--grid", choices=("full", "small"), default="full",
@@ -248,14 +264,18 @@ def main():
     if args.workload == "mixed_set":
         return main_set(args, torch, lx, W)
     wl = {"dimer": W.dimer_workload, "birth_death": W.birth_death_workload,
-          "telegraph": W.telegraph_workload,
-          "dimer_rathinam": W.rathinam_workload}[args.workload]()
+          "telegraph": W.telegraph_workload, "dimer_rathinam": W.rathinam_workload,
+          "random48x128": W.random_network_workload,
+          "stiff_padded45": W.stiff_padded_workload}[args.workload]()
+    if args.t_end > 0.0:
+        wl.t_end = args.t_end
     net = wl.nets[0]
     h = lx.Network(net.m, net.p)
     theta = torch.as_tensor(wl.theta[0], device="cuda")
     x0 = torch.as_tensor(wl.x0[0], device="cuda")
     best, table = tune(lx, h, theta, x0, wl.t_end, wl.eps, wl.mode, args.precision,
-                       grid=SMALL_GRID if args.grid == "small" else None,
+                       grid=(LARGE_GRID if h.large else
+                             SMALL_GRID if args.grid == "small" else None),
                        log=lambda s: print(s, flush=True))
     ms = min(t for o, t in table if o == best)
     key = key_of(net.m, net.p, wl.P, args.precision, wl.mode, wl.theta[0], wl.x0[0])

@@ -20,13 +20,18 @@
 
 namespace lx {
 
+// A pointer into LDS typed as such: accesses through it are LDS instructions
+// also where the compiler cannot see where it came from (the Newton solve is
+// an out-of-line function).
+#define LX_LDS __attribute__((address_space(3)))
+
 // Species counts of one lane in LDS: element i at p[i * LX_BLOCK] (the
 // table-driven loops index them at run time; LDS answers in tens of cycles
 // where the private segment, not resident in any cache at these sizes, takes
 // a trip to memory).
 struct XSlot {
-  int* p;
-  __device__ __forceinline__ int& operator[](int i) const { return p[i * LX_BLOCK]; }
+  LX_LDS int* p;
+  __device__ __forceinline__ LX_LDS int& operator[](int i) const { return p[i * LX_BLOCK]; }
 };
 
 template <class NET, class XV>
@@ -37,8 +42,8 @@ __device__ __forceinline__ double g_large(int j, const XV& x) {
   return gj;
 }
 
-template <class NET>
-__device__ __forceinline__ double g_large_y(int j, const double* y) {
+template <class NET, class YP>
+__device__ __forceinline__ double g_large_y(int j, YP y) {
   double gj = 1.0;
   for (int q = NET::RX_PTR[j]; q < NET::RX_PTR[j + 1]; ++q)
     gj = gj * binom_real(y[NET::RX_SP[q]], NET::RX_RO[q]);
@@ -46,8 +51,8 @@ __device__ __forceinline__ double g_large_y(int j, const double* y) {
 }
 
 // d g_j / d y_k.
-template <class NET>
-__device__ __forceinline__ double dg_large(int j, int k, const double* y) {
+template <class NET, class YP>
+__device__ __forceinline__ double dg_large(int j, int k, YP y) {
   double gj = 1.0;
   for (int q = NET::RX_PTR[j]; q < NET::RX_PTR[j + 1]; ++q) {
     const int i = NET::RX_SP[q];
@@ -58,8 +63,8 @@ __device__ __forceinline__ double dg_large(int j, int k, const double* y) {
 
 // d g_j / d y_k from the caller's terms of reactant slot q (reaction j, its
 // species k): JT_SLOT_T lists them in table order (as dg_user).
-template <class NET>
-__device__ __forceinline__ double dg_user_large(int q, const double* y) {
+template <class NET, class YP>
+__device__ __forceinline__ double dg_user_large(int q, YP y) {
   double s = 0.0;
   for (int u = NET::JT_SLOT_PTR[q]; u < NET::JT_SLOT_PTR[q + 1]; ++u) {
     const int t = NET::JT_SLOT_T[u];
@@ -586,8 +591,8 @@ __device__ __forceinline__ int wave_sum_int(int v) {
 }
 
 // g_j(y) with y_k replaced by yk (a forward-difference evaluation).
-template <class NET>
-__device__ __forceinline__ double g_large_moved(int j, int k, const double* y, double yk) {
+template <class NET, class YP>
+__device__ __forceinline__ double g_large_moved(int j, int k, YP y, double yk) {
   double gj = 1.0;
   for (int q = NET::RX_PTR[j]; q < NET::RX_PTR[j + 1]; ++q) {
     const int i = NET::RX_SP[q];
@@ -605,6 +610,16 @@ __device__ __forceinline__ double g_large_moved(int j, int k, const double* y, d
 // rounded.  In: S.tau, S.jc, S.th, S.ncr and the Poisson draws S.k, species
 // counts xs; out: the rounded counts in S.k when the solve converged.
 // Called by every lane of the wave.
+// Entries of an LU row loaded per step: 8, except in kernels compiled for
+// three or more waves per SIMD, whose register budget (168 or less) the
+// larger chunk would exceed (the out-of-line solve adds its registers to the
+// kernel's).
+#if defined(LX_WAVES) && LX_WAVES >= 3
+constexpr int LU_CHUNK = 1;
+#else
+constexpr int LU_CHUNK = 8;
+#endif
+
 struct NewtonOut {
   int iters;
   bool converged;
@@ -613,8 +628,10 @@ struct NewtonOut {
 };
 
 template <class NET, class XV>
-__device__ __noinline__ NewtonOut newton_core(SolveArea<NET>& S, const XV& xs, const SimParams& prm) {
+__device__ __noinline__ NewtonOut newton_core(SolveArea<NET>& S_area, const XV& xs,
+                                              const SimParams& prm) {
   constexpr int N = NET::N, M = NET::M, LD = SolveArea<NET>::LD;
+  LX_LDS SolveArea<NET>& S = *(LX_LDS SolveArea<NET>*)&S_area;
   const int lid = threadIdx.x & 63;
   const double tau = S.tau;
   const int jc = S.jc;
@@ -669,7 +686,7 @@ __device__ __noinline__ NewtonOut newton_core(SolveArea<NET>& S, const XV& xs, c
     if (lid < N) {
       const int i = lid;
       double si = 0.0;
-      double* Ai = S.A + i * LD;
+      LX_LDS double* Ai = S.A + i * LD;
       for (int kk = 0; kk < N; ++kk) Ai[kk] = 0.0;
       for (int q = NET::NI_PTR[i]; q < NET::NI_PTR[i + 1]; ++q) {
         const int j = NET::NI_RX[q];
@@ -707,11 +724,25 @@ __device__ __noinline__ NewtonOut newton_core(SolveArea<NET>& S, const XV& xs, c
       }
       if (lid < N) lp = lp == cc ? piv : (lp == piv ? cc : lp);
       const int pr = __ffsll((long long)__ballot(lid < N && lp == cc)) - 1;
-      const double* Ap = S.A + pr * LD;
+      const LX_LDS double* Ap = S.A + pr * LD;
       if (lid < N && lp > cc) {
-        double* Ai = S.A + lid * LD;
+        LX_LDS double* Ai = S.A + lid * LD;
         const double l = Ai[cc] / Ap[cc];
-        for (int q = cc; q < N; ++q) Ai[q] = Ai[q] - l * Ap[q];
+        // in chunks of LU_CHUNK: the chunk's loads all issue before its
+        // stores (the compiler cannot tell that row Ai is not row Ap); per
+        // entry the same operations
+        int q = cc;
+        for (; q + LU_CHUNK <= N; q += LU_CHUNK) {
+          double ai[LU_CHUNK], ap[LU_CHUNK];
+#pragma unroll
+          for (int u = 0; u < LU_CHUNK; ++u) {
+            ai[u] = Ai[q + u];
+            ap[u] = Ap[q + u];
+          }
+#pragma unroll
+          for (int u = 0; u < LU_CHUNK; ++u) Ai[q + u] = ai[u] - l * ap[u];
+        }
+        for (; q < N; ++q) Ai[q] = Ai[q] - l * Ap[q];
         S.b[lid] = S.b[lid] - l * S.b[pr];
       }
       wave_sync();
@@ -720,9 +751,22 @@ __device__ __noinline__ NewtonOut newton_core(SolveArea<NET>& S, const XV& xs, c
       // back substitution, logical rows from the last (sequential)
       for (int rr = N - 1; rr >= 0; --rr) {
         if (lid < N && lp == rr) {
-          const double* Ai = S.A + lid * LD;
+          const LX_LDS double* Ai = S.A + lid * LD;
           double sum = S.b[lid];
-          for (int q = rr + 1; q < N; ++q) sum = sum - Ai[q] * S.sol[q];
+          // ascending q as in the sequential form, operands loaded LU_CHUNK
+          // at a time
+          int q = rr + 1;
+          for (; q + LU_CHUNK <= N; q += LU_CHUNK) {
+            double ai[LU_CHUNK], sv[LU_CHUNK];
+#pragma unroll
+            for (int u = 0; u < LU_CHUNK; ++u) {
+              ai[u] = Ai[q + u];
+              sv[u] = S.sol[q + u];
+            }
+#pragma unroll
+            for (int u = 0; u < LU_CHUNK; ++u) sum = sum - ai[u] * sv[u];
+          }
+          for (; q < N; ++q) sum = sum - Ai[q] * S.sol[q];
           S.sol[rr] = sum / Ai[rr];
         }
         wave_sync();
@@ -788,7 +832,7 @@ __device__ void coop_newton(LaneL<P, NET, GRID>& me, int s, SolveArea<NET>& S, c
     for (int j = 0; j < M; ++j) S.k[j] = me.kd[j];
   }
   wave_sync();
-  const NewtonOut o = newton_core<NET>(S, XSlot{const_cast<int*>(xcol_s)}, prm);
+  const NewtonOut o = newton_core<NET>(S, XSlot{(LX_LDS int*)xcol_s}, prm);
   if (mine) {
     me.n_nit += o.iters;
     me.pend_ok = o.converged;
@@ -831,7 +875,7 @@ __device__ __forceinline__ void run_large(long long blk, const double* __restric
   SolveArea<NET>& S = areas[wave];
   const int* xwave = xlds + (threadIdx.x & ~63);
   LaneL<LX_POLICY, NET, LX_GRID_ON> lane;
-  lane.x.p = xlds + threadIdx.x;
+  lane.x.p = (LX_LDS int*)(xlds + threadIdx.x);
   lane.pend = false;
   if (has) lane.load(p, theta, x0, r_out, G_out, prm);
   while (__ballot(has) != 0ull) {
@@ -886,7 +930,7 @@ extern "C" __global__ void __launch_bounds__(64)
   if (q >= prm.P) return;
   __shared__ int xlds[LxNet::N * LX_BLOCK];
   lx::LaneL<LX_POLICY, LxNet> lane;
-  lane.x.p = xlds + threadIdx.x;
+  lane.x.p = (LX_LDS int*)(xlds + threadIdx.x);
   lx::SimParams p2 = prm;
   p2.accumulate = 0;
   p2.pid_base = 0;
@@ -921,7 +965,7 @@ extern "C" __global__ void __launch_bounds__(64)
   __shared__ int xlds[LxNet::N * 64];
   __shared__ lx::SolveArea<LxNet> S;
   lx::LaneL<lx::F64, LxNet> lane;
-  lane.x.p = xlds + threadIdx.x;
+  lane.x.p = (LX_LDS int*)(xlds + threadIdx.x);
   lx::SimParams p2 = prm;
   p2.accumulate = 0;
   p2.pid_base = 0;

@@ -350,6 +350,16 @@ def random_network_workload(P=65536, seed=4, omega=100.0) -> Workload:
                     "adaptive", theta=[th], x0=[x0], pid=[np.arange(P, dtype=np.int64)])
 
 
+def stiff_padded_workload(P=16384, n_pad=45) -> Workload:
+    """The stiff padded network (48 species, 94 reactions): about 270
+    implicit leaps with 48 x 48 Newton systems per trajectory to t_end 4."""
+    net = stiff_padded(n_pad)
+    th, x0 = tile(net, P)
+    return Workload(f"stiff dimer + {n_pad} birth-death species (N={net.N} M={net.M}) t_end=4",
+                    [net], P, 4.0, "adaptive", theta=[th], x0=[x0],
+                    pid=[np.arange(P, dtype=np.int64)])
+
+
 def telegraph_workload(P=1 << 18, seed=5) -> Workload:
     net = telegraph()
     th = gamma_prior_theta(net, P, seed)
