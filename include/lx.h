@@ -112,8 +112,10 @@ typedef struct lx_options {
   int64_t max_steps;    /* attempt budget per trajectory      default 10^7 (< 2^32) */
   int32_t lanes_per_wave; /* batched: active lanes per wave, 4/8/16/32/64; 0 = chosen from P */
   int32_t ssa_k;        /* batched: SSA steps per leap iteration, 1..64; 0 = default 4 */
-  int32_t blocks_per_cu;/* batched: resident blocks per CU, 1..8; 0 = default 2 (4 for
-                           networks beyond 16 species or 32 reactions) */
+  int32_t blocks_per_cu;/* batched: resident blocks per CU, 1..8; 0 = default 2 (for
+                           networks beyond 16 species or 32 reactions: as many as their
+                           LDS fits, at most 8, with one trajectory per wave; 4 with one
+                           per lane) */
   uint32_t pid_stride;  /* row p uses RNG particle id pid_base + p * pid_stride;
                            0 means 1 (interleaved ids for sharding or mixed sets) */
   int32_t regroup;      /* batched: every `regroup` iterations the lanes of a block are

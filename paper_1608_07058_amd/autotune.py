@@ -49,8 +49,7 @@ SMALL_GRID = {
 # Networks beyond 16 species or 32 reactions (one trajectory per wave): the
 # block size sets how many waves share one Newton area in LDS.
 LARGE_GRID = {
-    "block_size": (64, 128, 192, 256),
-    "blocks_per_cu": (4,),
+    "block_size": (64, 128, 192, 256),  # blocks per CU: as many as their LDS fits
 }
 
 

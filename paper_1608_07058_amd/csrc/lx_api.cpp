@@ -708,7 +708,10 @@ lx_status plan_sim(lx_network net, int64_t P, const lx_options& o, double t_end,
       st = device_cus(&cus);
       if (st != LX_OK) return st;
       const long long round = L->block / 64;
-      const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : 4);
+      // default: as many blocks per CU as their LDS lets be resident (at most 8)
+      long long fit = 163840 / wave_lds_bytes(*net, o.precision, L->block);
+      fit = fit < 1 ? 1 : (fit > 8 ? 8 : fit);
+      const long long max_grid = (long long)cus * (o.blocks_per_cu ? o.blocks_per_cu : fit);
       long long per_block = (P + max_grid - 1) / max_grid;
       if (per_block < round) per_block = round;
       L->prm.per_block = per_block;
