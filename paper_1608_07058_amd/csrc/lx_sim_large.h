@@ -563,31 +563,67 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Wave reductions with DPP moves (VALU, no LDS round trip): row shifts by 1,
+// 2, 4 and 8 leave each row's result in its lane 15, two row broadcasts
+// combine the rows into lane 63, which every lane then reads.  `ident` is
+// what a lane without a source reads.  Only for operations whose result
+// does not depend on the order (max, min, integer sums).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_b32(int v, int ident) {
+  return __builtin_amdgcn_update_dpp(ident, v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS, class T>
+__device__ __forceinline__ T dpp_move(T v, T ident) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, dpp_b32<CTRL, ROWS>(__builtin_bit_cast(int, v),
+                                                     __builtin_bit_cast(int, ident)));
+  } else {
+    static_assert(sizeof(T) == 8, "32- or 64-bit values");
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long c = __builtin_bit_cast(unsigned long long, ident);
+    const unsigned lo = (unsigned)dpp_b32<CTRL, ROWS>((int)(unsigned)b, (int)(unsigned)c);
+    const unsigned hi = (unsigned)dpp_b32<CTRL, ROWS>((int)(unsigned)(b >> 32), (int)(unsigned)(c >> 32));
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T read_lane(T v, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+  } else {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
+
+template <class T, class Op>
+__device__ __forceinline__ T wave_reduce(T v, T ident, Op op) {
+  v = op(v, dpp_move<0x111, 0xF>(v, ident));  // row_shr:1
+  v = op(v, dpp_move<0x112, 0xF>(v, ident));  // row_shr:2
+  v = op(v, dpp_move<0x114, 0xF>(v, ident));  // row_shr:4
+  v = op(v, dpp_move<0x118, 0xF>(v, ident));  // row_shr:8
+  v = op(v, dpp_move<0x142, 0xA>(v, ident));  // row_bcast:15 into rows 1, 3
+  v = op(v, dpp_move<0x143, 0xC>(v, ident));  // row_bcast:31 into rows 2, 3
+  return read_lane(v, 63);
+}
+
 // Wave maximum of values >= 0 (a NaN counts as 0, as the sequential
 // max(m, v) = (m < v ? v : m) from 0 skips it).
 __device__ __forceinline__ double wave_max_nonneg(double v) {
   v = v == v ? v : 0.0;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const double w = __shfl_xor(v, o, 64);
-    v = v < w ? w : v;
-  }
-  return v;
+  return wave_reduce(v, 0.0, [](double a, double b) { return a < b ? b : a; });
 }
 
 __device__ __forceinline__ int wave_min_int(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const int w = __shfl_xor(v, o, 64);
-    v = w < v ? w : v;
-  }
-  return v;
+  return wave_reduce(v, 0x7fffffff, [](int a, int b) { return b < a ? b : a; });
 }
 
 __device__ __forceinline__ int wave_sum_int(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return wave_reduce(v, 0, [](int a, int b) { return a + b; });
 }
 
 // g_j(y) with y_k replaced by yk (a forward-difference evaluation).
@@ -716,7 +752,7 @@ __device__ __noinline__ NewtonOut newton_core(SolveArea<NET>& S_area, const XV& 
       const double best = wave_max_nonneg(vm < 0.0 ? 0.0 : vm);
       const unsigned long long at_cc = __ballot(cand && lp == cc);
       const int lane_cc = __ffsll((long long)at_cc) - 1;
-      const double vcc = __shfl(v, lane_cc, 64);
+      const double vcc = read_lane(v, lane_cc);
       const int piv = wave_min_int((cand && vm == best && vm >= 0.0) ? lp : 0x7fffffff);
       if (!(vcc == vcc) || !(best > 0.0) || piv == 0x7fffffff) {
         lu_ok = false;

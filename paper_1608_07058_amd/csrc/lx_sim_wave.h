@@ -77,12 +77,7 @@ struct WaveArea {
 template <class R>
 __device__ __forceinline__ R wave_min_r(R v) {
   v = v == v ? v : (R)__builtin_inf();
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const R w = __shfl_xor(v, o, 64);
-    v = w < v ? w : v;
-  }
-  return v;
+  return wave_reduce(v, (R)__builtin_inf(), [](R a, R b) { return b < a ? b : a; });
 }
 
 template <class P, class NET, bool GRID = false>
