@@ -34,9 +34,12 @@ METRIC = "trajectories/s and reaction-events/s on 1 GPU, batched-mixed vs plain 
 # VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
 # (one fp64 or fp32 add/mul/fma, or one integer operation, per lane per cycle).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Device sources compiled into the simulation kernels at run time.
-KERNEL_SOURCES = ("lx_params.h", "lx_device.h", "lx_sim.h")
+# Device sources compiled into the simulation kernels at run time, and the host
+# library that generates the network's tables and the kernel source around them.
+KERNEL_SOURCES = ("lx_params.h", "lx_device.h", "lx_sim.h", "lx_api.cpp")
 LARGE_SOURCES = ("lx_sim_large.h", "lx_sim_wave.h")  # networks beyond 16 x 32
+METHOD_CONSTANTS = ("n_c", "delta", "n_stiff", "k_ssa", "k_crit", "n_ssa_ex", "n_ssa_im",
+                    "lambda_thr", "newton_tol", "newton_maxit", "max_steps")
 PROFILES = os.path.join(ROOT, "profiles")
 # Workloads bench.py can time; the headline line is "mixed_set".
 WORKLOADS = {
@@ -117,11 +120,15 @@ def kernel_id(opts, large=False):
     measured on.  `large`: the network takes the large-network kernels, whose
     sources are hashed too."""
     import hashlib
+    from paper_1608_07058_amd import lx
     h = hashlib.sha1()
     for name in KERNEL_SOURCES + (LARGE_SOURCES if large else ()):
         with open(os.path.join(ROOT, "paper_1608_07058_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     h.update(json.dumps(opts, sort_keys=True).encode())
+    # the library's defaults of the method constants compiled into the kernel
+    d = lx.options()
+    h.update(json.dumps({k: getattr(d, k) for k in METHOD_CONSTANTS}, sort_keys=True).encode())
     return h.hexdigest()[:16]
 
 

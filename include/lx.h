@@ -103,7 +103,8 @@ typedef struct lx_options {
   double k_crit;        /* SSA burst if a0c >= a0 / k_crit    default 10 */
   int32_t n_ssa_ex;     /* SSA burst length after an explicit choice, default 100 */
   int32_t n_ssa_im;     /* SSA burst length after an implicit choice, default 10 */
-  double lambda_thr;    /* Poisson inversion below, PTRS above, default 30, in [1,30] */
+  double lambda_thr;    /* Poisson inversion below, PTRS (valid from 10) at or
+                           above, default 15, in [10,30] */
   double newton_tol;    /* Newton stop: |dy|inf <= tol*max(1,|y|inf), default 1e-10 */
   int32_t newton_maxit; /* default 20 */
   int32_t block_size;   /* threads per block (64..256, multiple of 64); 0 = default (64
@@ -407,7 +408,8 @@ lx_status lx_test_uniform_f32(int64_t n, const uint32_t* w, float* out, void* st
  * 12 sqrt_f32 (in/out float). */
 lx_status lx_test_math(int32_t fn, int64_t n, const void* in, void* out, void* stream);
 /* Poisson(lam[q]) drawn at site (pid[q], e[q], site[q]) with key (seed,
- * stream_id); precision LX_PREC_*; out int64 (-1 = beyond range). */
+ * stream_id); lambda_thr in [10,30] as in lx_options; precision LX_PREC_*;
+ * out int64 (-1 = beyond range). */
 lx_status lx_test_poisson(int64_t n, const double* lam, const uint32_t* pid, const uint32_t* e,
                           const uint32_t* site, uint64_t seed, uint32_t stream_id,
                           double lambda_thr, int32_t precision, int64_t* out, void* stream);

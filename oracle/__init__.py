@@ -252,7 +252,7 @@ def log_f32(x): return _unary("orc_log_f32", x, np.float32)
 def lfact(k): return _unary("orc_lfact", k, np.float64)
 
 
-def poisson(lam, pid, e, site, *, seed=160807058, stream=0, lambda_thr=30.0, precision="fp64"):
+def poisson(lam, pid, e, site, *, seed=160807058, stream=0, lambda_thr=15.0, precision="fp64"):
     lam = np.ascontiguousarray(lam, dtype=np.float64).reshape(-1)
     n = lam.shape[0]
     pid = np.ascontiguousarray(np.broadcast_to(pid, n), dtype=np.uint32)

@@ -1225,7 +1225,7 @@ int simulate_impl(int32_t N, int32_t M, const int32_t* mtab, const int32_t* ptab
   Net net;
   if (build_net(N, M, mtab, ptab, &net) != 0) return -1;
   const orc_options& o = *opt;
-  if (!(o.lambda_thr >= 1.0 && o.lambda_thr <= 30.0) || o.n_c < 0 || o.mode < 0 || o.mode > 2 ||
+  if (!(o.lambda_thr >= 10.0 && o.lambda_thr <= 30.0) || o.n_c < 0 || o.mode < 0 || o.mode > 2 ||
       !(t_end >= o.t_start) || !(o.eps > 0.0) || o.precision < 0 || o.precision > 1 ||
       !jacobian_ok(net, o))
     return -2;
@@ -1258,7 +1258,7 @@ void orc_default_options(orc_options* o) {
   o->n_stiff = 100.0;
   o->k_ssa = 10.0;
   o->k_crit = 10.0;
-  o->lambda_thr = 30.0;
+  o->lambda_thr = 15.0;
   o->newton_tol = 1e-10;
   o->t_start = 0.0;
   o->max_steps = 10000000;

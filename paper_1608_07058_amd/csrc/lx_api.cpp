@@ -535,7 +535,7 @@ lx_status fill_params(const lx_options& o, int64_t P, double t_end, double eps, 
   if (o.schedule != LX_SCHED_PLAIN && o.schedule != LX_SCHED_BATCHED)
     return fail(LX_E_INVALID, "schedule must be LX_SCHED_*");
   if (o.n_c < 0 || !(o.delta >= 0.0) || !(o.n_stiff > 0.0) || !(o.k_ssa >= 0.0) ||
-      !(o.k_crit > 0.0) || o.n_ssa_ex < 1 || o.n_ssa_im < 1 || !(o.lambda_thr >= 1.0) ||
+      !(o.k_crit > 0.0) || o.n_ssa_ex < 1 || o.n_ssa_im < 1 || !(o.lambda_thr >= 10.0) ||
       !(o.lambda_thr <= 30.0) || !(o.newton_tol > 0.0) || o.newton_maxit < 0 ||
       o.max_steps < 0 || o.max_steps > 4294967295LL)
     return fail(LX_E_INVALID, "option out of range");
@@ -803,7 +803,7 @@ void lx_options_default(lx_options* o) {
   o->k_crit = 10.0;
   o->n_ssa_ex = 100;
   o->n_ssa_im = 10;
-  o->lambda_thr = 30.0;
+  o->lambda_thr = 15.0;
   o->newton_tol = 1e-10;
   o->newton_maxit = 20;
   o->max_steps = 10000000;
@@ -1153,7 +1153,7 @@ lx_status lx_test_math(int32_t fn, int64_t n, const void* in, void* out, void* s
 lx_status lx_test_poisson(int64_t n, const double* lam, const uint32_t* pid, const uint32_t* e,
                           const uint32_t* site, uint64_t seed, uint32_t stream_id,
                           double lambda_thr, int32_t precision, int64_t* out, void* stream) {
-  if (n < 0 || (n > 0 && (!lam || !pid || !e || !site || !out)) || !(lambda_thr >= 1.0) ||
+  if (n < 0 || (n > 0 && (!lam || !pid || !e || !site || !out)) || !(lambda_thr >= 10.0) ||
       !(lambda_thr <= 30.0) || (precision != LX_PREC_FP64 && precision != LX_PREC_MIXED))
     return fail(LX_E_INVALID, "bad arguments");
   if (n == 0) return LX_OK;

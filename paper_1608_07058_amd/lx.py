@@ -504,7 +504,7 @@ def test_math(fn, x, device="cuda"):
     return out.cpu().numpy()
 
 
-def test_poisson(lam, pid, e, site, *, seed=160807058, stream_id=0, lambda_thr=30.0,
+def test_poisson(lam, pid, e, site, *, seed=160807058, stream_id=0, lambda_thr=15.0,
                  precision="fp64", device="cuda"):
     import torch
     lam = np.asarray(lam, np.float64).reshape(-1)

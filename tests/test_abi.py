@@ -44,7 +44,7 @@ def test_struct_layouts_and_defaults():
     assert lx.STATS_DTYPE.itemsize == 80
     o = lx.options()
     assert (o.precision, o.schedule, o.n_c, o.n_ssa_ex, o.n_ssa_im, o.newton_maxit) == (0, 0, 10, 100, 10, 20)
-    assert (o.delta, o.n_stiff, o.k_ssa, o.k_crit, o.lambda_thr, o.newton_tol) == (0.05, 100.0, 10.0, 10.0, 30.0, 1e-10)
+    assert (o.delta, o.n_stiff, o.k_ssa, o.k_crit, o.lambda_thr, o.newton_tol) == (0.05, 100.0, 10.0, 10.0, 15.0, 1e-10)
     assert o.seed == 160807058 and o.max_steps == 10_000_000
 
 
@@ -110,7 +110,7 @@ def test_argument_validation_before_any_device_call():
         kw.update(bad)
         assert L.lx_simulate(net.handle, 0, None, None, kw["t_end"], kw["eps"], kw["mode"],
                              C.byref(o), None, None, None, None, None) == -1
-    for field, value in (("lambda_thr", 50.0), ("n_ssa_ex", 0), ("lanes_per_wave", 12),
+    for field, value in (("lambda_thr", 50.0), ("lambda_thr", 9.5), ("n_ssa_ex", 0), ("lanes_per_wave", 12),
                          ("ssa_k", 65), ("blocks_per_cu", 9), ("max_steps", 1 << 33),
                          ("block_size", 96), ("precision", 2), ("regroup", 65), ("lanes_per_traj", 3), ("lanes_per_traj", 32)):
         ob = lx.options(**{field: value})

@@ -166,14 +166,16 @@ def test_rejection_sequence_hand_worked(orc, precision):
 
 def test_inversion_draws_of_the_hand_worked_case_are_exact_quantiles(orc):
     # The hand-worked sequence above takes its counts from the oracle's
-    # inversion sampler; pin those draws to the exact Poisson quantile of the
-    # site's binary64 uniform (away from rounding ties of the summed CDF).
+    # sampler: means below 15 (the default threshold) from the inversion,
+    # pinned here to the exact Poisson quantile of the site's binary64 uniform
+    # (away from rounding ties of the summed CDF); means of 15 and more from
+    # PTRS, whose law and final test are pinned in test_oracle_samplers.
     pid = np.arange(2000, dtype=np.uint32)
     n = len(pid)
     ctr = np.stack([pid, np.full(n, 4), np.zeros(n), np.zeros(n)], 1).astype(np.uint32)
     key = np.tile(np.array([160807058, 0], np.uint32), (n, 1))
     u = orc.uniform_f64(orc.philox(ctr, key)[:, :2])
-    for lam in (10.0, 5.0, 2.5, 37.0 * 0.5):
+    for lam in (10.0, 5.0, 2.5, 37.0 * 0.25, 14.999):
         k = orc.poisson(np.full(len(pid), lam), pid, 4, 0)
         ref = stats.poisson.ppf(u, lam)
         near = np.abs(stats.poisson.cdf(ref, lam) - u) < 1e-12
@@ -192,7 +194,7 @@ def _holm_ok(pvals, alpha=0.01):
 def test_binary32_instance_matches_binary64_in_distribution(orc, name, mode, t_end):
     # 10^5 trajectories of each policy, independent streams: per output a
     # two-sample KS test (Holm-adjusted p > 0.01), means and variances within
-    # 3 standard errors.
+    # 4.5 standard errors (about 20 such checks per case).
     net = getattr(W, name)()
     P = 100000
     th, x0 = W.tile(net, P)
@@ -209,11 +211,11 @@ def test_binary32_instance_matches_binary64_in_distribution(orc, name, mode, t_e
                 continue
             pv.append(stats.ks_2samp(u, v).pvalue)
             se_m = math.sqrt(u.var() / P + v.var() / P)
-            assert abs(u.mean() - v.mean()) <= 3 * se_m + 1e-12 * abs(u.mean()), (key, c)
+            assert abs(u.mean() - v.mean()) <= 4.5 * se_m + 1e-12 * abs(u.mean()), (key, c)
             # SE of a sample variance: sqrt((m4 - s^4) / n)
             def se_var(w):
                 d = w - w.mean()
                 return math.sqrt(max((d**4).mean() - w.var()**2, 0.0) / P)
             se_v = math.sqrt(se_var(u)**2 + se_var(v)**2)
-            assert abs(u.var() - v.var()) <= 3 * se_v + 1e-12 * u.var(), (key, c)
+            assert abs(u.var() - v.var()) <= 4.5 * se_v + 1e-12 * u.var(), (key, c)
     assert _holm_ok(pv), pv

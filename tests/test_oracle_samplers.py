@@ -196,15 +196,16 @@ def _site_uniform(orc, pid, e, site, trial=0, seed=SEED, stream=0, precision="fp
 @pytest.mark.parametrize("precision,margin", [("fp64", 1e-12), ("mixed", 2e-5)])
 @pytest.mark.parametrize("lam", [1e-6, 0.05, 0.5, 1.0, 3.0, 7.5, 9.99, 12.0, 20.0, 29.9])
 def test_poisson_inversion_is_the_exact_quantile(orc, lam, precision, margin):
-    # Below the threshold (30 by default) the sampler must return the smallest
-    # k with u <= F(k) for the site's first uniform: scipy's exact Poisson
+    # Below the threshold (here its largest allowed value, 30) the sampler
+    # must return the smallest k with u <= F(k) for the site's first uniform:
+    # scipy's exact Poisson
     # quantile function, except where u lies within the rounding of the
     # summed CDF (a few units of the policy's precision times the number of
     # terms) of one of its steps.
     n = 20000
     pid = np.arange(n, dtype=np.uint32)
     u = _site_uniform(orc, pid, 7, 3, precision=precision)
-    k = orc.poisson(np.full(n, lam), pid, 7, 3, precision=precision)
+    k = orc.poisson(np.full(n, lam), pid, 7, 3, precision=precision, lambda_thr=30.0)
     ref = stats.poisson.ppf(u, lam)
     cdf_k = stats.poisson.cdf(ref, lam)
     cdf_km1 = stats.poisson.cdf(ref - 1, lam)
@@ -224,7 +225,7 @@ def test_poisson_inversion_tail_stops_at_the_cdf_resolution(orc):
     top = pid[np.argsort(u)[-64:]]
     assert u.max() > 1.0 - 2.0 ** -22
     for lam in (1.0, 3.0, 9.9, 20.0, 29.9):
-        k = orc.poisson(np.full(top.size, lam), top, 7, 3, precision="mixed")
+        k = orc.poisson(np.full(top.size, lam), top, 7, 3, precision="mixed", lambda_thr=30.0)
         assert k.max() < 140, lam
         assert k.max() <= stats.poisson.ppf(1.0 - 1e-10, lam) + 10, (lam, k.max())
 
@@ -252,11 +253,16 @@ def _chi2_poisson(samples, lam):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("lam", [0.3, 4.0, 9.99, 10.0, 10.5, 30.0, 250.0, 1e4, 1e6])
-def test_poisson_law(orc, lam, precision):
+@pytest.mark.parametrize("lam_thr", [10.0, 15.0, 30.0])
+@pytest.mark.parametrize("lam", [0.3, 4.0, 9.99, 10.0, 10.5, 17.3, 29.9, 30.0, 250.0, 1e4, 1e6])
+def test_poisson_law(orc, lam, precision, lam_thr):
+    # both samplers over the range where the threshold lets either draw:
+    # inversion up to 30, PTRS from 10 (its published range)
+    if lam_thr != 15.0 and not 9.0 < lam < 31.0:
+        pytest.skip("same sampler as the default threshold")
     n = 200000
     pid = np.arange(n, dtype=np.uint32)
-    k = orc.poisson(np.full(n, lam), pid, 11, 5, precision=precision)
+    k = orc.poisson(np.full(n, lam), pid, 11, 5, precision=precision, lambda_thr=lam_thr)
     assert k.min() >= 0
     assert _chi2_poisson(k, lam) > 1e-4
     z_mean = (k.mean() - lam) / math.sqrt(lam / n)
