@@ -362,22 +362,29 @@ __device__ __forceinline__ bool ptrs_candidate(const PtrsParams<P>& c, const Wor
   const R us = (R)0.5 - P::fabs_(u);
   const R kf = P::floor_((((R)2 * c.a) / us + c.b) * u + c.lam + (R)0.43);
   if constexpr (P::mixed) {
-    // binary32: all outcomes of the transformed-rejection test evaluated
-    // without branches (a wave nearly always holds a lane that needs the
-    // density test): out of range, quick acceptance, quick rejection,
-    // density test.  A candidate out of range takes the test at k = 0,
-    // harmlessly; the accepted set is the one of the sequential test.  In
-    // binary64 the density test costs more than the branches it saves.
+    // binary32: the outcomes of the transformed-rejection test evaluated
+    // without per-lane branches: out of range, quick acceptance, quick
+    // rejection, and the density test, which the wave computes for all its
+    // lanes when any of them needs it (a full wave nearly always holds one;
+    // a wave down to a few trajectories often does not).  A candidate out of
+    // range takes the test at k = 0, harmlessly; the accepted set is the one
+    // of the sequential test.  In binary64 the density test costs more than
+    // the branches it saves.
     const bool range = (kf >= (R)0) & ((double)kf <= 1073741824.0);
     const bool quick = (us >= (R)0.07) & (v <= c.vr);
     const bool qrej = (us < (R)0.013) & (v > us);
     const R ks = range ? kf : (R)0;
-    const R hat = c.a / (us * us) + c.b;
-    R fac, rhs;
-    ptrs_log_density<P>(ks, c.lam, &fac, &rhs);
-    const R lhs = P::ulog(((v * c.inv_alpha) * fac) / hat);
     *k = (long long)ks;
-    return range & (quick | (!qrej & (lhs <= rhs)));
+    bool accept = range & quick;
+    const bool test = range & !quick & !qrej;
+    if (__ballot(test) != 0ull) {
+      const R hat = c.a / (us * us) + c.b;
+      R fac, rhs;
+      ptrs_log_density<P>(ks, c.lam, &fac, &rhs);
+      const R lhs = P::ulog(((v * c.inv_alpha) * fac) / hat);
+      accept = accept | (test & (lhs <= rhs));
+    }
+    return accept;
   } else {
     if (kf < (R)0 || (double)kf > 1073741824.0) return false;
     if (us >= (R)0.07 && v <= c.vr) {
