@@ -655,8 +655,11 @@ long long wave_lds_bytes(const lx_network_s& n, int precision, int block) {
 }
 
 int wave_default_waves(const lx_network_s& n, int precision, int block) {
-  const long long blocks = 163840 / wave_lds_bytes(n, precision, block);
-  const long long reach = blocks * (block / 64) / 4;
+  // waves per SIMD of the blocks the LDS lets be resident (at most 8 per CU),
+  // rounded up, so that the register budget never keeps one of them out
+  long long blocks = 163840 / wave_lds_bytes(n, precision, block);
+  blocks = blocks > 8 ? 8 : blocks;
+  const long long reach = (blocks * (block / 64) + 3) / 4;
   return (int)(reach < 1 ? 1 : (reach > WAVE_KERNEL_WAVES ? WAVE_KERNEL_WAVES : reach));
 }
 
