@@ -152,8 +152,10 @@ typedef struct lx_options {
                            still running in a wave, the wave gives each of them a group
                            of tail_lanes lanes (as lanes_per_traj) to finish it; 0 = off
                            (default), 2, 4, 8 or 16.  Results unchanged */
-  int32_t waves_per_simd; /* register budget: 0 = the compiler's choice (default; 4 for
-                           the one-trajectory-per-wave kernel of large networks), else
+  int32_t waves_per_simd; /* register budget: 0 = the compiler's choice (default; for
+                           the one-trajectory-per-wave kernel of large networks, the
+                           waves per SIMD of the blocks its LDS lets be resident,
+                           rounded up, at most 4), else
                            1..8 -- the kernel is compiled to keep at least this many
                            waves resident per SIMD (fewer registers per lane, spills if
                            needed).  Results unchanged */
