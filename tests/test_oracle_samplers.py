@@ -254,7 +254,8 @@ def _chi2_poisson(samples, lam):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("lam_thr", [10.0, 15.0, 30.0])
-@pytest.mark.parametrize("lam", [0.3, 4.0, 9.99, 10.0, 10.5, 17.3, 29.9, 30.0, 250.0, 1e4, 1e6])
+@pytest.mark.parametrize("lam", [0.3, 4.0, 9.99, 10.0, 10.5, 14.99, 15.0, 17.3, 29.9, 30.0, 250.0, 1e4,
+                                 1e6])
 def test_poisson_law(orc, lam, precision, lam_thr):
     # both samplers over the range where the threshold lets either draw:
     # inversion up to 30, PTRS from 10 (its published range)
