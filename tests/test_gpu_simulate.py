@@ -106,6 +106,27 @@ def test_simulate_matches_oracle_elementwise(lxm, orc, case, precision, schedule
     assert np.all(got["stats"]["status"] == 0)
 
 
+@pytest.mark.parametrize("lam_thr", [10.0, 30.0])
+@pytest.mark.parametrize("schedule", ["plain", "batched", "group4"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_poisson_threshold_option_matches_oracle(lxm, orc, lam_thr, precision, schedule):
+    # the two ends of the allowed Poisson threshold: the dimer's and Schloegl's
+    # leaps draw means on both sides of each
+    for net, t_end in ((W.dimer(), 30.0), (W.schlogl(), 10.0)):
+        P = 600
+        theta = W.gamma_prior_theta(net, P, seed=41)
+        _, x0 = W.tile(net, P)
+        kw = {"group4": dict(schedule="batched", lanes_per_traj=4)}.get(schedule,
+                                                                          dict(schedule=schedule))
+        got = gpu_run(lxm, net, theta, x0, t_end, "adaptive", precision=precision,
+                      lambda_thr=lam_thr, **kw)
+        ref = orc.simulate(net.m, net.p, theta, x0, t_end, mode="adaptive", precision=precision,
+                           lambda_thr=lam_thr)
+        assert_same(got, ref, f"{net.name}/{precision}/{schedule}/lambda_thr {lam_thr}")
+    with pytest.raises(lxm.LxError):
+        gpu_run(lxm, net, theta[:2], x0[:2], t_end, "adaptive", lambda_thr=9.5)
+
+
 @pytest.mark.parametrize("schedule", ["plain", "batched", "group4"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name,t_end", [("dimer_stiff", 3.0), ("dimer_rathinam", 2.0),
