@@ -115,10 +115,11 @@ def copy_calibration(args):
 
 
 def kernel_id(opts, large=False):
-    """Hash of the kernel sources and the launch options of one form: HBM traffic
-    measured with hardware counters is reported only for the kernel it was
-    measured on.  `large`: the network takes the large-network kernels, whose
-    sources are hashed too."""
+    """Hash of the kernel sources, the host code that generates the kernel
+    source, the launch options of one form and the library's method
+    constants: HBM traffic measured with hardware counters is reported only
+    for the kernel it was measured on.  `large`: the network takes the
+    large-network kernels, whose sources are hashed too."""
     import hashlib
     from paper_1608_07058_amd import lx
     h = hashlib.sha1()
