@@ -424,6 +424,13 @@ def test_bad_inputs_and_budgets(orc):
     assert res["stats"]["status"][0] == 4
     with pytest.raises(ValueError):
         orc.simulate([[4]], [[0]], [[1.0]], [[1]], 1.0)   # order > 3
+    # the Poisson threshold stays where both samplers are exact: PTRS is
+    # published for means of 10 and more, the inversion's cap is set for 30
+    for bad in (9.5, 30.5):
+        with pytest.raises(ValueError):
+            orc.simulate([[1]], [[0]], [[1.0]], [[5]], 1.0, lambda_thr=bad)
+    for ok in (10.0, 30.0):
+        orc.simulate([[1]], [[0]], [[1.0]], [[5]], 1.0, lambda_thr=ok)
 
 
 def test_newton_failures_fall_back_and_stay_valid(orc):
